@@ -1,0 +1,354 @@
+"""Workload descriptions and seeded synthetic initial data.
+
+This module is shared by the HIP path's driver and by the CPU oracle.  It holds
+only *input synthesis*: run configurations (mesh sizes, boundary kinds, gas and
+scheme constants) and seeded generators that return primitive fields
+(density, velocity, pressure) at given points.  It contains none of the
+method's arithmetic: no equation of state, no conversion to conserved
+variables, no fluxes.  Each consumer turns the primitive fields into its own
+conserved state.
+
+Geometry convention: the domain is the box [lo, hi) in every dimension; level
+``l`` has ``base_cells * 2**l`` cells per dimension of width
+``h_l = (hi - lo) / (base_cells * 2**l)``; cell ``g`` has its sample point at
+``lo + (g + 1/2) h_l`` (cell-centred reading of the nodal mesh of Section 2.2).
+
+The paper's demonstrations (Section 5) use R = 1 and gamma = 1.4; the
+implosion problem is its Eq. (13).  The other generators are synthetic
+stand-ins with the shapes and value ranges of the benchmark configurations:
+shock tubes, four-state Riemann quadrants with density blobs, spherical blast
+waves and a k^-2 density perturbation field.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, List, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# run configurations
+# ---------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class AMRConfig:
+    name: str
+    dim: int
+    base_cells: int                 # level-0 cells per dimension
+    patch_cells: List[int]          # patch edge (cells) per level
+    periodic: List[bool]            # per dimension; False = transmissive
+    lo: float = 0.0
+    hi: float = 1.0
+    gamma: float = 1.4
+    cfl: float = 0.5
+    weno_eps: float = 1e-6
+    tag_theta: float = 0.02
+    tag_buffer: int = 2
+    regrid_interval: int = 4
+    steps: int = 100
+    max_patches: int = 4096
+    ic: str = "uniform"
+    ghost: int = 4
+
+    @property
+    def max_levels(self) -> int:
+        return len(self.patch_cells)
+
+    @property
+    def nvar(self) -> int:
+        return self.dim + 2
+
+    def cells(self, level: int) -> int:
+        return self.base_cells * (2 ** level)
+
+    def h(self, level: int) -> float:
+        return (self.hi - self.lo) / self.cells(level)
+
+    def patches_per_dim(self, level: int) -> int:
+        n = self.patch_cells[level]
+        c = self.cells(level)
+        if c % n:
+            raise ValueError(f"level {level}: {c} cells not divisible by patch {n}")
+        return c // n
+
+    def validate(self) -> None:
+        if self.dim not in (1, 2, 3):
+            raise ValueError("dim must be 1, 2 or 3")
+        if len(self.periodic) != self.dim:
+            raise ValueError("periodic needs one entry per dimension")
+        for l, n in enumerate(self.patch_cells):
+            if n < 4 or n % 2:
+                raise ValueError("patch edge must be even and >= 4")
+            self.patches_per_dim(l)
+            if l + 1 < self.max_levels:
+                nf = self.patch_cells[l + 1]
+                if (2 * n) % nf:
+                    raise ValueError("fine patch edge must divide twice the coarse edge")
+
+    def replace(self, **kw) -> "AMRConfig":
+        return dataclasses.replace(self, **kw)
+
+
+def _cfg(**kw) -> AMRConfig:
+    c = AMRConfig(**kw)
+    c.validate()
+    return c
+
+
+CONFIGS = {
+    # 1D shock tube, 2 levels, 16-cell patches, transmissive, per-patch launches.
+    "c1": _cfg(name="c1", dim=1, base_cells=256, patch_cells=[16, 16],
+               periodic=[False], steps=200, regrid_interval=4, ic="shock_tube",
+               max_patches=256),
+    # 2D quadrants + blobs, 3 levels, 32/16/16 patches, periodic.
+    "c2": _cfg(name="c2", dim=2, base_cells=256, patch_cells=[32, 16, 16],
+               periodic=[True, True], steps=500, regrid_interval=4,
+               ic="quadrants_blobs", max_patches=16384),
+    # 3D blast waves, 4 levels, uneven 32/16/16/8 patches, periodic.
+    "c3": _cfg(name="c3", dim=3, base_cells=128, patch_cells=[32, 16, 16, 8],
+               periodic=[True] * 3, steps=50, regrid_interval=4, ic="blasts",
+               max_patches=65536),
+    # 2D quadrants + blobs on 512^2, 5 levels of 32^2 patches.
+    "c4": _cfg(name="c4", dim=2, base_cells=512, patch_cells=[32] * 5,
+               periodic=[True, True], steps=200, regrid_interval=8,
+               tag_buffer=4, ic="quadrants_blobs", max_patches=65536),
+    # 3D blast waves + k^-2 density perturbations, base 256^3.
+    "c5": _cfg(name="c5", dim=3, base_cells=256, patch_cells=[32, 16, 16, 8],
+               periodic=[True] * 3, steps=200, regrid_interval=8, tag_buffer=4,
+               ic="blasts_perturbed", max_patches=131072),
+    # The paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2.
+    "implosion": _cfg(name="implosion", dim=2, base_cells=256,
+                      patch_cells=[32, 16, 16], periodic=[True, True],
+                      lo=-0.3, hi=0.3, cfl=0.45, steps=200, ic="implosion",
+                      max_patches=16384),
+}
+
+
+def config(name: str, **overrides) -> AMRConfig:
+    c = CONFIGS[name].replace(**overrides) if overrides else CONFIGS[name]
+    c.validate()
+    return c
+
+
+# ---------------------------------------------------------------------------
+# geometry helpers (sample points only)
+# ---------------------------------------------------------------------------
+
+
+def patch_points(cfg: AMRConfig, level: int, coord: Sequence[int],
+                 ghost: int = 0) -> List[np.ndarray]:
+    """Sample points of a patch's cells, optionally including ``ghost`` layers.
+
+    Returns ``[x, y, z][:dim]``, each of shape ``(m,)*dim`` in array axis order
+    (z, y, x) with x varying along the last axis; ``m = n + 2*ghost``.
+    Points of ghost cells beyond a periodic boundary are not wrapped.
+    """
+    n = cfg.patch_cells[level]
+    h = cfg.h(level)
+    d = cfg.dim
+    axes = []
+    for j in range(d):
+        g = coord[j] * n + np.arange(-ghost, n + ghost)
+        axes.append(cfg.lo + (g + 0.5) * h)
+    # meshgrid in (z, y, x) order so that x is the last axis
+    grids = np.meshgrid(*reversed(axes), indexing="ij")
+    return list(reversed(grids))
+
+
+def _min_image(dx: np.ndarray, length: float) -> np.ndarray:
+    return dx - length * np.round(dx / length)
+
+
+# ---------------------------------------------------------------------------
+# seeded initial-data generators: each returns f(points) -> (rho, [u_j], p)
+# ---------------------------------------------------------------------------
+
+Prim = Callable[[List[np.ndarray]], tuple]
+
+
+def uniform_state(dim: int, seed: int) -> Prim:
+    """A constant random state: rho, p ~ U[0.2, 2], u_j ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.2, 2.0)
+    p = rng.uniform(0.2, 2.0)
+    u = [rng.uniform(-1.0, 1.0) for _ in range(dim)]
+
+    def f(pts):
+        shape = pts[0].shape
+        return (np.full(shape, rho), [np.full(shape, uj) for uj in u],
+                np.full(shape, p))
+    return f
+
+
+def density_wave(dim: int, k: Sequence[int], velocity: Sequence[float],
+                 amp: float = 0.2, length: float = 1.0, t: float = 0.0) -> Prim:
+    """rho = 1 + amp sin(2 pi k.(x - u t)/L), u constant, p = 1 (smooth)."""
+
+    def f(pts):
+        phase = np.zeros_like(pts[0])
+        for j in range(dim):
+            phase = phase + k[j] * (pts[j] - velocity[j] * t)
+        rho = 1.0 + amp * np.sin(2.0 * np.pi * phase / length)
+        return (rho, [np.full_like(rho, velocity[j]) for j in range(dim)],
+                np.ones_like(rho))
+    return f
+
+
+def shock_tube(seed: int) -> Prim:
+    """1D Riemann problem: rho_L, p_L, rho_R, p_R ~ U[0.1, 1], x0 ~ U[0.3, 0.7], u = 0."""
+    rng = np.random.default_rng(seed)
+    rl, pl, rr, pr = (rng.uniform(0.1, 1.0) for _ in range(4))
+    x0 = rng.uniform(0.3, 0.7)
+
+    def f(pts):
+        x = pts[0]
+        left = x < x0
+        return (np.where(left, rl, rr), [np.zeros_like(x)], np.where(left, pl, pr))
+    f.params = dict(rho_l=rl, p_l=pl, rho_r=rr, p_r=pr, x0=x0)
+    return f
+
+
+def quadrants_blobs(seed: int, lo: float = 0.0, hi: float = 1.0) -> Prim:
+    """Four constant Riemann states plus 8 Gaussian density blobs (periodic)."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for _ in range(4):  # (x<1/2,y<1/2), (>=,<), (<,>=), (>=,>=)
+        rho = rng.uniform(0.2, 1.5)
+        p = rng.uniform(0.2, 1.5)
+        u = rng.uniform(-0.5, 0.5)
+        v = rng.uniform(-0.5, 0.5)
+        quads.append((rho, u, v, p))
+    blobs = []
+    L = hi - lo
+    for _ in range(8):
+        cx = lo + L * rng.uniform(0.0, 1.0)
+        cy = lo + L * rng.uniform(0.0, 1.0)
+        amp = rng.uniform(0.1, 0.5)
+        w = L * rng.uniform(0.02, 0.05)
+        blobs.append((cx, cy, amp, w))
+    mid = lo + 0.5 * L
+
+    def f(pts):
+        x, y = pts[0], pts[1]
+        q = (x >= mid).astype(int) + 2 * (y >= mid).astype(int)
+        tab = np.array(quads)
+        rho = tab[q, 0].copy()
+        u = tab[q, 1]
+        v = tab[q, 2]
+        p = tab[q, 3]
+        for cx, cy, amp, w in blobs:
+            dx = _min_image(x - cx, L)
+            dy = _min_image(y - cy, L)
+            rho = rho + amp * np.exp(-(dx * dx + dy * dy) / (w * w))
+        return rho, [u, v], p
+    return f
+
+
+def _blast_sources(rng, dim: int, lo: float, L: float):
+    src = []
+    for _ in range(6):
+        c = [lo + L * rng.uniform(0.0, 1.0) for _ in range(dim)]
+        pj = rng.uniform(5.0, 50.0)
+        rad = L * rng.uniform(0.03, 0.08)
+        src.append((c, pj, rad))
+    return src
+
+
+def _blast_pressure(src, pts, dim: int, L: float) -> np.ndarray:
+    p = np.ones_like(pts[0])
+    for c, pj, rad in src:
+        r2 = np.zeros_like(pts[0])
+        for j in range(dim):
+            dj = _min_image(pts[j] - c[j], L)
+            r2 = r2 + dj * dj
+        p = np.where(r2 < rad * rad, np.maximum(p, pj), p)
+    return p
+
+
+def blasts(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0) -> Prim:
+    """rho = 1, u = 0, p = 1 except inside 6 spheres where p = p_jump (ratio reading)."""
+    rng = np.random.default_rng(seed)
+    L = hi - lo
+    src = _blast_sources(rng, dim, lo, L)
+
+    def f(pts):
+        p = _blast_pressure(src, pts, dim, L)
+        return (np.ones_like(p), [np.zeros_like(p) for _ in range(dim)], p)
+    return f
+
+
+def blasts_perturbed(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0,
+                     amp: float = 0.05, kmax: int = 8) -> Prim:
+    """Blast waves plus a random-phase density field with shell power ~ k^-2.
+
+    delta_rho = sum_k A_k cos(2 pi k.x / L + phi_k) over integer wave vectors
+    with 1 <= |k| <= kmax in a half space, A_k ~ |k|^-2, phases ~ U[0, 2 pi);
+    the amplitudes are scaled so that sum_k A_k = amp, which bounds
+    max |delta_rho| by amp.
+    """
+    rng = np.random.default_rng(seed)
+    L = hi - lo
+    src = _blast_sources(rng, dim, lo, L)
+    modes = []
+    rngk = range(-kmax, kmax + 1)
+    for kz in (rngk if dim == 3 else [0]):
+        for ky in (rngk if dim >= 2 else [0]):
+            for kx in rngk:
+                k = (kx, ky, kz)[:dim]
+                kk = sum(c * c for c in k)
+                if kk == 0 or kk > kmax * kmax:
+                    continue
+                # half space: first nonzero component (z, y, x order) positive
+                first = next(c for c in reversed(k) if c != 0)
+                if first < 0:
+                    continue
+                modes.append((k, kk ** -1.0))
+    phases = rng.uniform(0.0, 2.0 * np.pi, len(modes))
+    total = sum(a for _, a in modes)
+
+    def f(pts):
+        p = _blast_pressure(src, pts, dim, L)
+        drho = np.zeros_like(pts[0])
+        for (k, a), ph in zip(modes, phases):
+            arg = np.full_like(pts[0], ph)
+            for j in range(dim):
+                arg = arg + 2.0 * np.pi * k[j] * (pts[j] - lo) / L
+            drho = drho + (amp * a / total) * np.cos(arg)
+        return (1.0 + drho, [np.zeros_like(p) for _ in range(dim)], p)
+    return f
+
+
+def implosion(lo: float = -0.3, hi: float = 0.3) -> Prim:
+    """Eq. (13): (rho, p) = (0.125, 0.14) inside |x| + |y| < 0.15, else (1, 1); at rest."""
+
+    def f(pts):
+        x, y = pts[0], pts[1]
+        inside = np.abs(x) + np.abs(y) < 0.15
+        rho = np.where(inside, 0.125, 1.0)
+        p = np.where(inside, 0.140, 1.0)
+        return rho, [np.zeros_like(x), np.zeros_like(x)], p
+    return f
+
+
+def initial_data(cfg: AMRConfig, seed: int) -> Prim:
+    """The seeded generator named by ``cfg.ic``."""
+    if cfg.ic == "shock_tube":
+        return shock_tube(seed)
+    if cfg.ic == "quadrants_blobs":
+        return quadrants_blobs(seed, cfg.lo, cfg.hi)
+    if cfg.ic == "blasts":
+        return blasts(seed, cfg.dim, cfg.lo, cfg.hi)
+    if cfg.ic == "blasts_perturbed":
+        return blasts_perturbed(seed, cfg.dim, cfg.lo, cfg.hi)
+    if cfg.ic == "implosion":
+        return implosion(cfg.lo, cfg.hi)
+    if cfg.ic == "uniform":
+        return uniform_state(cfg.dim, seed)
+    raise KeyError(cfg.ic)
+
+
+def seed_for(config_index: int, run: int) -> int:
+    """Seed of run ``run`` of configuration ``config_index`` (1-based)."""
+    return 1000 * config_index + run
