@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the AMR Euler hot path on one MI355X.
+
+One step = one SSP-RK3 time step over every leaf patch of every level (CFL
+time step, three stages of ghost fill + fused WENO5/Rusanov/divergence/RK
+combine + coarse/fine flux correction + restriction), plus the gradient tag
+and regrid every ``regrid_interval`` steps, on seeded synthetic data already
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--config c2] [--exec batched|per_patch]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "FP64 cell-updates/s (all levels) + % HBM roofline; batched+learned vs plain"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+
+
+def flops_per_cell_stage(d: int, stage: int) -> int:
+    """Algorithmic FP64 operations of one cell in one RK stage, counted on the
+    definitions (add, mul, div, sqrt = 1; one edge and one face per cell and
+    direction): primitives 3d+4; per direction 2(d+2) WENO5-JS evaluations of
+    66 operations, two edge states of 4d+10, Rusanov 5(d+2), face flux
+    5(d+2), divergence 3(d+2); the stage combination 2 (stage 1) or 5
+    operations per variable."""
+    nv = d + 2
+    weno = 2 * nv * 66
+    flux = 2 * (4 * d + 10) + 5 * nv
+    per_dir = weno + flux + 5 * nv + 3 * nv
+    combine = (2 if stage == 1 else 5) * nv
+    return (3 * d + 4) + d * per_dir + combine
+
+
+def bytes_per_cell_stage(d: int, stage: int) -> int:
+    """Algorithmic HBM bytes of one cell in one stage: read U^n (and the stage
+    input at stages 2-3), write the output; FP64, d+2 variables."""
+    return (2 if stage == 1 else 3) * (d + 2) * 8
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, seed: int):
+    """The oracle, as it stands, on a bounded sample: one SSP-RK3 step over the
+    initial hierarchy of the same workload."""
+    from paper_2508_05020_amd import workloads
+    from oracle.solver import OracleAMR
+    o = OracleAMR(cfg)
+    o.init_from_ic(workloads.initial_data(cfg, seed))
+    cells = o.leaf_cells()
+    t0 = time.perf_counter()
+    o.step()
+    dt = time.perf_counter() - t0
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one SSP-RK3 step of the {cfg.name} initial hierarchy "
+                      f"({cells} leaf cells, seed {seed}), numpy FP64, single thread, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--seed", type=int, default=2001)
+    ap.add_argument("--exec", dest="exec_mode", default="batched", choices=["batched", "per_patch"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is described in the design notes, not built.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2508_05020_amd import amr, workloads
+
+    cfg = workloads.config(args.config)
+    mode = amr.EXEC_BATCHED if args.exec_mode == "batched" else amr.EXEC_PER_PATCH
+    h = amr.Hierarchy(cfg, exec_mode=mode)
+    amr.init_from_ic(h, workloads.initial_data(cfg, args.seed))
+    log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
+        f"{h.leaf_cells()} leaf cells")
+
+    nstep = 0
+
+    def advance(k: int, count: bool):
+        nonlocal nstep
+        cells = 0
+        for _ in range(k):
+            if count:
+                cells += h.leaf_cells()
+            h.step()
+            nstep += 1
+            if cfg.regrid_interval > 0 and nstep % cfg.regrid_interval == 0:
+                h.adapt()
+        return cells
+
+    advance(args.warmup, False)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cells = advance(args.steps, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches, kcells = h.profile_read()
+    h.profile(False)
+    elapsed = t1 - t0
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; stage kernel "
+        f"{launches} launches, {ms:.2f} ms")
+    if h.check() != 0:
+        log("[bench] WARNING: non-physical cells after the run")
+
+    d = cfg.dim
+    f_step = sum(flops_per_cell_stage(d, s) for s in (1, 2, 3))
+    b_step = sum(bytes_per_cell_stage(d, s) for s in (1, 2, 3))
+    # every timed step launches the stage kernel once per stage over all leaf
+    # cells (batched) or once per tile group (per-patch): totals per step
+    total_flops = cells * f_step
+    total_bytes = cells * b_step
+    kern_s = ms * 1e-3
+    achieved_tf = total_flops / kern_s / 1e12 if kern_s > 0 else 0.0
+    achieved_gbs = total_bytes / kern_s / 1e9 if kern_s > 0 else 0.0
+    value = cells / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / max(1, args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{cfg.name}: {d}D Euler gamma={cfg.gamma}, base {cfg.base_cells}^{d}, "
+                        f"{cfg.max_levels} levels, patches {cfg.patch_cells}, "
+                        f"{'periodic' if all(cfg.periodic) else 'mixed bc'}, ic {cfg.ic} "
+                        f"seed {args.seed}, CFL {cfg.cfl}, regrid every {cfg.regrid_interval}",
+            "exec": args.exec_mode,
+            "leaf_cells_per_step_avg": cells / max(1, args.steps),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_stage (fused WENO5-JS + Rusanov + Eq. (9) divergence + RK combine)",
+            "achieved": achieved_tf,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "launches": launches,
+            "avg_launch_ms": ms / max(1, launches),
+            "flops_per_cell_update": f_step,
+        },
+        "roofline_hbm": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "bytes_per_cell_update": b_step,
+            "whole_step_frac": cells * b_step / elapsed / 1e9 / HBM_PEAK_GBS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+    print(json.dumps(out), flush=True)
+    h.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,219 @@
+/*
+ * libamr -- MI355X (gfx950) AMR compressible-Euler hot path, C ABI.
+ *
+ * The library advances the compressible Euler equations (Section 2.1 of
+ * "Task-Based Programming for Adaptive Mesh Refinement in Compressible Flow
+ * Simulations", Eq. (1)-(7); calorically perfect gas, R = 1) on a forest of
+ * equal-shape patches (Section 3.2) that obeys the validity rules R1/R2 and is
+ * adapted by the recursive refinement and the coarsening procedures of
+ * Section 3.3 (Algorithms 1 and 2).  Fluxes are WENO5-JS interpolated
+ * primitives (p, T, u_j) combined by the Rusanov solver (Eq. (10)-(12)); the
+ * divergence is the 4th-order staggered difference of Eq. (9), written in
+ * conservative face-flux form; time advancement is SSP-RK3 (Section 2.2).
+ * All solution arithmetic is FP64.
+ *
+ * Conventions shared by every call
+ *  - Patch data are cell-centred.  A patch of level l has n_l cells per
+ *    dimension plus ng = 4 ghost layers on every side; its storage is
+ *    structure-of-arrays, var-major: [var][z][y][x] over the full
+ *    (n_l + 8)^dim box, x fastest.  Variables are (rho, rho u_x[, rho u_y
+ *    [, rho u_z]], rho e).
+ *  - "pid" is a patch slot index in [0, max_patches).  Slots are partitioned
+ *    by level; a pid's level never changes while it is active.
+ *  - State buffers: 0 = U^n, 1 = A, 2 = B (the two SSP-RK3 stage buffers).
+ *  - Calls marked "async" enqueue work on the hierarchy's HIP stream and
+ *    return; calls marked "sync" wait for that stream before returning.
+ *  - Device pointers ("_dev") are caller-owned device memory; host pointers
+ *    ("_host") are caller-owned host memory.  The library never frees either.
+ *  - Every call returns an amr_status; on failure amr_last_error() gives a
+ *    message.  No C++ exception crosses this interface.  A hierarchy is not
+ *    re-entrant: one thread (and one stream) per hierarchy.
+ */
+#ifndef AMR_H
+#define AMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amr_hierarchy amr_hierarchy;
+
+typedef enum {
+  AMR_OK = 0,
+  AMR_E_ARG = -1,          /* invalid argument or configuration */
+  AMR_E_CAPACITY = -2,     /* patch pool exhausted; hierarchy unchanged */
+  AMR_E_HIP = -3,          /* a HIP runtime call failed */
+  AMR_E_MESH = -4,         /* R1/R2 or a ghost/prolongation source missing */
+  AMR_E_NONPHYSICAL = -5,  /* rho <= 0, p <= 0 or NaN in a leaf cell */
+  AMR_E_STATE = -6         /* call not valid in the current state */
+} amr_status;
+
+enum { AMR_MAX_LEVELS = 8, AMR_GHOST = 4 };
+enum { AMR_EXEC_PER_PATCH = 0, AMR_EXEC_BATCHED = 1 };
+enum { AMR_COARSEN_TEXT = 0, AMR_COARSEN_LITERAL = 1 };
+enum { AMR_SCHEME_WENO = 0, AMR_SCHEME_CENTRAL = 1 };
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` bytes aligned to 256 B, or NULL. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} amr_allocator;
+
+/* Run configuration (Section 3.2: fixed-capacity patch pool `np_max`, patch
+ * size, ghost width; Section 5: gamma, R = 1, CFL). */
+typedef struct {
+  int dim;                           /* 1, 2 or 3 */
+  int max_levels;                    /* 1 .. AMR_MAX_LEVELS */
+  int base_cells;                    /* level-0 cells per dimension */
+  int patch_cells[AMR_MAX_LEVELS];   /* patch edge n_l; even, >= 4; n_{l+1} | 2 n_l */
+  int periodic[3];                   /* per dimension: 1 periodic, 0 transmissive */
+  double lo, hi;                     /* domain [lo, hi)^dim */
+  double gamma;                      /* ratio of specific heats (1.4) */
+  double cfl;                        /* dt = cfl / max_leaf sum_j (|u_j| + c) / h_l */
+  double weno_eps;                   /* WENO5-JS epsilon (1e-6) */
+  double tag_theta;                  /* gradient tag threshold (0.02) */
+  int tag_buffer;                    /* tag dilation in cells (0 .. 3) */
+  int max_patches;                   /* total patch slots over all levels */
+  int level_capacity[AMR_MAX_LEVELS];/* slots per level; 0 = derive from max_patches */
+  int exec_mode;                     /* AMR_EXEC_PER_PATCH or AMR_EXEC_BATCHED */
+  int coarsen_rule;                  /* AMR_COARSEN_TEXT (default) or _LITERAL */
+  int scheme;                        /* AMR_SCHEME_WENO (default) or _CENTRAL */
+} amr_config;
+
+/* One row of the patch table (Fig. grid-meta of the paper: level, nbr,
+ * parent, child, plus the patch position). */
+typedef struct {
+  int32_t pid;
+  int32_t level;
+  int32_t coord[3];      /* patch position on its level, (x, y, z) */
+  int32_t parent;        /* -1 on level 0 */
+  int32_t nchildren;     /* 0 for a leaf */
+  int32_t first_child;   /* lowest child pid, -1 for a leaf */
+  int32_t nbr[26];       /* Moore neighbours in (dz, dy, dx) lexicographic
+                            order, dx fastest, centre skipped; 3^dim - 1
+                            entries used; -1 = absent or physical boundary */
+} amr_patch_info;
+
+/* Create a hierarchy holding every level-0 patch (sync).  `alloc` may be
+ * NULL (hipMalloc is used); `hip_stream` may be NULL (default stream).
+ * Device memory: 3 state buffers, one flux-register pool and the tables,
+ * all sized from max_patches so that regridding never reallocates.
+ * Errors: AMR_E_ARG for an invalid config, AMR_E_HIP on allocation failure;
+ * on failure *out still receives an object whose amr_last_error() explains
+ * the failure and which must be passed to amr_destroy_hierarchy. */
+amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* alloc,
+                                void* hip_stream, amr_hierarchy** out);
+amr_status amr_destroy_hierarchy(amr_hierarchy* h);
+const char* amr_last_error(const amr_hierarchy* h);
+
+/* Sizes and layout queries (no device work). */
+amr_status amr_num_patches(const amr_hierarchy* h, int* nactive, int* nleaf);
+amr_status amr_patch_doubles(const amr_hierarchy* h, int level, int64_t* n);
+amr_status amr_state_doubles(const amr_hierarchy* h, int64_t* n);
+amr_status amr_patch_offset(const amr_hierarchy* h, int pid, int64_t* off);
+amr_status amr_state_ptr(const amr_hierarchy* h, int buf, double** dev);
+
+/* Active patches sorted by (level, z, y, x); writes at most `cap` rows and
+ * the total count to *n (sync). */
+amr_status amr_get_patch_table(const amr_hierarchy* h, amr_patch_info* out, int cap, int* n);
+
+/* Upload / download whole patch arrays (ghosts included) for `npatch` pids;
+ * the host buffer is the concatenation of the patches' arrays in `pids`
+ * order (sync).  amr_set_state_prim takes interior primitive values
+ * (rho, u_x[, u_y[, u_z]], p), var-major over n_l^dim cells per patch, and
+ * stores E = p / (gamma - 1) + rho u.u / 2 (Eq. (4), (6)). */
+amr_status amr_set_state(amr_hierarchy* h, int buf, const double* host, const int* pids, int npatch);
+amr_status amr_get_state(const amr_hierarchy* h, int buf, double* host, const int* pids, int npatch);
+amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* host_prim,
+                              const int* pids, int npatch);
+
+/* Ghost fill of every active patch of buffer `buf` (async): same-level
+ * source where an active same-level patch covers the (wrapped or clamped)
+ * ghost position, otherwise conservative MC-limited linear prolongation
+ * from the level below (multi-resolution support required by R2). */
+amr_status amr_fill_ghosts(amr_hierarchy* h, int buf);
+
+/* L(U) of buffer `buf` on every leaf patch (async), including the
+ * coarse/fine flux correction: Section 2.2 fluxes and Eq. (9) divergence.
+ * Ghosts of `buf` are filled first.  rhs_dev has amr_state_doubles()
+ * entries in the state-buffer layout; leaf interiors are written. */
+amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev);
+
+/* dt = cfl / max over leaf cells of buffer `buf` of sum_j (|u_j| + c) / h_l,
+ * with c from Eq. (7); written to the device scalar *dt_dev (async). */
+amr_status amr_compute_dt(amr_hierarchy* h, int buf, double* dt_dev);
+
+/* One SSP-RK3 stage (1, 2 or 3; async): fill ghosts of the stage input,
+ * fused RHS + stage combination on every leaf, coarse/fine flux correction,
+ * restriction of every non-leaf patch.  dt is read from the device scalar. */
+amr_status amr_rk_stage(amr_hierarchy* h, int stage, const double* dt_dev);
+
+/* dt (into *dt_dev) followed by the three stages (async). */
+amr_status amr_step(amr_hierarchy* h, double* dt_dev);
+
+/* Gradient tagging of buffer `buf` (async; ghosts are filled first).
+ * Per pid (max_patches entries each): refine_req = leaf below the finest
+ * level with a tagged cell within tag_buffer cells of its interior;
+ * coarsen_req = patch whose children are all leaves without tags
+ * (the requests of Fig. grid-meta).  cell_tags_dev (nullable) receives the
+ * dilated per-cell tag of every leaf interior cell, one byte per cell in a
+ * layout of (n_l + 8)^dim bytes per patch at offset amr_patch_offset/nvar. */
+amr_status amr_tag(amr_hierarchy* h, int buf, uint8_t* refine_req_dev,
+                   uint8_t* coarsen_req_dev, uint8_t* cell_tags_dev);
+
+/* Apply refinement (Algorithm 1, recursive) then coarsening (Algorithm 2)
+ * requests given per pid on the host (sync).  New patches of U^n are
+ * prolonged from the level below.  Transactional: on AMR_E_CAPACITY the mesh
+ * is unchanged.  *ncreated / *ndeleted may be NULL. */
+amr_status amr_regrid(amr_hierarchy* h, const uint8_t* refine_req_host,
+                      const uint8_t* coarsen_req_host, int* ncreated, int* ndeleted);
+
+/* amr_tag on U^n followed by amr_regrid with those requests (sync). */
+amr_status amr_adapt(amr_hierarchy* h, int* ncreated, int* ndeleted);
+
+/* Count leaf cells of U^n with rho <= 0, p <= 0 or NaN (sync); returns
+ * AMR_E_NONPHYSICAL when the count is positive. */
+amr_status amr_check(amr_hierarchy* h, int* nonphysical_count);
+
+/* Pids created by the most recent regrid, in creation order (no device work). */
+amr_status amr_last_created(const amr_hierarchy* h, int* pids, int cap, int* n);
+
+/* Reads and returns the sticky ghost-fill/prolongation error flag: 1 when a
+ * fill found no same-level or coarser source for a ghost cell (invalid mesh)
+ * since the last regrid (sync). */
+amr_status amr_fill_error(amr_hierarchy* h, int* flag);
+
+/* Host-only replay of mesh adaptation, for checking the refinement and
+ * coarsening procedures without a GPU (no device work).  `req` holds `nreq`
+ * records of 6 int32: (round, kind, level, x, y, z) with kind 0 = refine
+ * request, 1 = coarsen request, sorted by round; each round's requests are
+ * applied as one regrid (Algorithm 1 then Algorithm 2) to a fresh base mesh.
+ * Requests naming an inactive position are ignored.  The resulting active
+ * patches are returned as by amr_get_patch_table (nbr not filled). */
+amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq,
+                             amr_patch_info* out, int cap, int* n);
+
+/* Number of leaf cells (sum of n_l^dim over leaf patches) of the current
+ * mesh (no device work): the cells one step advances. */
+amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells);
+
+/* Timing of the fused RHS + stage kernel: while enabled, every launch of it is
+ * bracketed by HIP events on the hierarchy's stream.  amr_profile (sync)
+ * enables/disables and resets; amr_profile_read (sync) returns the summed
+ * event time in ms, the number of launches and the leaf cells they covered. */
+amr_status amr_profile(amr_hierarchy* h, int enable);
+amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, int64_t* cells);
+
+/* Execution mode switch (AMR_EXEC_PER_PATCH launches one kernel per patch per
+ * phase; AMR_EXEC_BATCHED launches each phase once over all patches). */
+amr_status amr_set_exec_mode(amr_hierarchy* h, int mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMR_H */

@@ -1,0 +1,95 @@
+// Internal structures shared by the host mesh manager, the kernels and the
+// C-ABI layer of libamr.  Not part of the public interface (include/amr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/amr.h"
+
+namespace amr {
+
+constexpr int kNG = AMR_GHOST;   // ghost layers (flux-form Eq. (9) + WENO5 need 4)
+constexpr int kMaxLev = AMR_MAX_LEVELS;
+
+// Per-level constants, mirrored on the device by value.
+struct LevelC {
+  int n;             // patch edge (cells)
+  int full;          // n + 2 ng
+  int np;            // patches per dimension on this level
+  int cells;         // cells per dimension on this level
+  int pid_base;      // first pid of this level's slot range
+  int cap;           // slots of this level
+  int map_off;       // offset of this level's patch map (np^dim ints)
+  int ratio;         // children per dimension (2 n_l / n_{l+1}); 0 on the finest level
+  long long pool_off;  // offset (doubles) of this level's pool in a state buffer
+  long long stride;    // doubles per patch (nvar * full^dim)
+  long long fr_off;    // offset (doubles) of this level's flux-register pool
+  long long fr_stride; // doubles per patch of flux registers (2 dim nvar n^(dim-1))
+  long long tag_off;   // offset (bytes) of this level's cell-tag pool
+  double h, inv_h;
+};
+
+// Everything a kernel needs to address patch data, passed by value.
+struct DevMesh {
+  int dim, nvar, nlev, scheme;
+  int tile;           // tile edge of the fused stage kernel (cells)
+  int periodic[3];
+  int max_patches, maxc;
+  double gamma, gm1, igm1, eps, theta, cfl;
+  int tag_buffer;
+  LevelC lv[kMaxLev];
+  const int* level;    // [max_patches]
+  const int* coord;    // [max_patches * 3]
+  const int* parent;   // [max_patches]
+  const int* nchild;   // [max_patches]
+  const int* child;    // [max_patches * maxc]
+  const int* map;      // all levels' patch maps
+};
+
+// Work lists, all resident in one device int buffer.
+struct ListView {
+  const int* ptr;
+  int count;
+};
+
+// Launch wrappers implemented in kernels.hip.
+struct Kernels {
+  static void fill(const DevMesh& m, double* U, const int* list, int count, int* err,
+                   hipStream_t s);
+  static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
+                    double* out, double* fr, const int* tiles, int count,
+                    const double* lam, hipStream_t s);
+  static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
+                     const int* list, int count, const double* lam, double w,
+                     hipStream_t s);
+  static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
+                             hipStream_t s);
+  static void max_rate(const DevMesh& m, const double* U, const int* list, int count,
+                       unsigned long long* lam_bits, hipStream_t s);
+  static void zero_u64(unsigned long long* p, hipStream_t s);
+  static void dt_from_rate(const DevMesh& m, const unsigned long long* lam_bits,
+                           double* dt, hipStream_t s);
+  static void tag(const DevMesh& m, const double* U, const int* list, int count,
+                  uint8_t* has_tag, uint8_t* raw, hipStream_t s);
+  static void cell_tags(const DevMesh& m, const uint8_t* raw, const int* list, int count,
+                        uint8_t* out, hipStream_t s);
+  static void requests(const DevMesh& m, const uint8_t* has_tag, const uint8_t* active_leaf,
+                       int nslots, uint8_t* refine, uint8_t* coarsen, hipStream_t s);
+  static void prolong_new(const DevMesh& m, double* U, const int* list, int count, int* err,
+                          hipStream_t s);
+  static void scatter_int(int* dst, const int* pairs, int npairs, hipStream_t s);
+  static void check(const DevMesh& m, const double* U, const int* list, int count,
+                    int* bad, hipStream_t s);
+  // Largest supported tile edge dividing every level's patch edge (0: none).
+  static int choose_tile(int dim, const int* n, int nlev);
+  static int tiles_per_patch(int dim, int tile, int n);
+};
+
+// Stage modes of the fused RHS/combine kernel.
+enum StageMode { kModeRHS = 0, kModeStage1 = 1, kModeStage2 = 2, kModeStage3 = 3 };
+
+}  // namespace amr

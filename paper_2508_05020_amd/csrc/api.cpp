@@ -1,0 +1,917 @@
+// C-ABI layer of libamr: the hierarchy object, device tables and work lists,
+// and the sequencing of the kernels for each call of include/amr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "amr_internal.hpp"
+#include "forest.hpp"
+
+namespace {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct StateError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIP_OK(expr)                                                         \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      std::ostringstream os_;                                                \
+      os_ << #expr << ": " << hipGetErrorString(e_);                         \
+      throw HipError(os_.str());                                             \
+    }                                                                        \
+  } while (0)
+
+}  // namespace
+
+struct amr_hierarchy {
+  amr_config cfg{};
+  amr::Forest forest;
+  amr::DevMesh dm{};
+  hipStream_t stream = nullptr;
+  amr_allocator alloc{};
+  bool has_alloc = false;
+  std::string err;
+  int nvar = 0;
+  int exec_mode = AMR_EXEC_BATCHED;
+  std::vector<void*> owned;
+
+  // device memory
+  double* U[3] = {nullptr, nullptr, nullptr};
+  long long state_doubles = 0;
+  double* fr = nullptr;
+  long long fr_doubles = 0;
+  long long tag_bytes = 0;
+  int* d_tab = nullptr;  // level | parent | nchild | coord | child | map
+  long long tab_ints = 0;
+  long long off_level = 0, off_parent = 0, off_nchild = 0, off_coord = 0, off_child = 0,
+            off_map = 0;
+  uint8_t* d_active_leaf = nullptr;
+  uint8_t* d_has_tag = nullptr;
+  uint8_t* d_raw = nullptr;
+  uint8_t* d_refine = nullptr;
+  uint8_t* d_coarsen = nullptr;
+  unsigned long long* d_lam = nullptr;
+  double* d_dt = nullptr;
+  int* d_flags = nullptr;  // [0] fill/prolong error, [1] nonphysical count
+  int* d_lists = nullptr;
+  long long lists_cap = 0;
+  int* d_pairs = nullptr;
+  long long pairs_cap = 0;
+
+  // host mirrors of the work lists
+  std::vector<int> lists;
+  amr::ListView all{}, leaves{}, tiles{}, reflux{};
+  amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
+  std::vector<int> last_created;
+  std::vector<uint8_t> h_active_leaf;
+  long long leaf_cells = 0;
+
+  // optional timing of the fused stage kernel with HIP events
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<long long> ev_cells;
+  void prof_begin(hipEvent_t* a) {
+    if (ev_used + 2 > ev_pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        HIP_OK(hipEventCreate(&e));
+        ev_pool.push_back(e);
+      }
+    }
+    *a = ev_pool[ev_used++];
+    HIP_OK(hipEventRecord(*a, stream));
+  }
+  void prof_end(long long cells) {
+    hipEvent_t b = ev_pool[ev_used++];
+    HIP_OK(hipEventRecord(b, stream));
+    ev_cells.push_back(cells);
+  }
+
+  void* dev_alloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (has_alloc) {
+      p = alloc.alloc(bytes, alloc.ctx);
+      if (!p) throw HipError("device allocator returned NULL");
+    } else {
+      HIP_OK(hipMalloc(&p, bytes));
+    }
+    owned.push_back(p);
+    return p;
+  }
+  void release_all() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    ev_pool.clear();
+    for (void* p : owned) {
+      if (has_alloc) alloc.free(p, alloc.ctx);
+      else (void)hipFree(p);
+    }
+    owned.clear();
+  }
+  void check_launch() { HIP_OK(hipGetLastError()); }
+  void sync() { HIP_OK(hipStreamSynchronize(stream)); }
+};
+
+namespace {
+
+using amr::Kernels;
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+void validate_config(const amr_config& c) {
+  if (c.dim < 1 || c.dim > 3) throw ArgError("dim must be 1, 2 or 3");
+  if (c.max_levels < 1 || c.max_levels > AMR_MAX_LEVELS) throw ArgError("bad max_levels");
+  if (c.base_cells <= 0) throw ArgError("bad base_cells");
+  if (!(c.hi > c.lo)) throw ArgError("empty domain");
+  if (!(c.gamma > 1.0)) throw ArgError("gamma must exceed 1");
+  if (!(c.cfl > 0.0)) throw ArgError("cfl must be positive");
+  if (c.tag_buffer < 0 || c.tag_buffer > 3) throw ArgError("tag_buffer must be in 0..3");
+  if (c.max_patches <= 0) throw ArgError("max_patches must be positive");
+  for (int l = 0; l < c.max_levels; ++l) {
+    const int n = c.patch_cells[l];
+    if (n < 4 || n % 2) throw ArgError("patch edge must be even and >= 4");
+    if (((long long)c.base_cells << l) % n) throw ArgError("level cells not divisible by patch");
+    if (l + 1 < c.max_levels && (2 * n) % c.patch_cells[l + 1])
+      throw ArgError("fine patch edge must divide twice the coarse edge");
+  }
+  for (int j = 0; j < c.dim; ++j)
+    if (c.periodic[j] != 0 && c.periodic[j] != 1) throw ArgError("periodic flags are 0 or 1");
+  if (!Kernels::choose_tile(c.dim, c.patch_cells, c.max_levels))
+    throw ArgError("patch edges must be multiples of 8 (1D, 2D) or 4 (3D)");
+}
+
+void build_devmesh(amr_hierarchy* h) {
+  const amr_config& c = h->cfg;
+  amr::DevMesh& m = h->dm;
+  amr::Forest& f = h->forest;
+  m.dim = c.dim;
+  m.nvar = c.dim + 2;
+  m.nlev = c.max_levels;
+  m.scheme = c.scheme;
+  m.tile = Kernels::choose_tile(c.dim, c.patch_cells, c.max_levels);
+  for (int j = 0; j < 3; ++j) m.periodic[j] = j < c.dim ? c.periodic[j] : 1;
+  m.max_patches = c.max_patches;
+  m.maxc = f.maxc;
+  m.gamma = c.gamma;
+  m.gm1 = c.gamma - 1.0;
+  m.igm1 = 1.0 / m.gm1;
+  m.eps = c.weno_eps;
+  m.theta = c.tag_theta;
+  m.cfl = c.cfl;
+  m.tag_buffer = c.tag_buffer;
+  long long pool = 0, frp = 0, tg = 0;
+  for (int l = 0; l < c.max_levels; ++l) {
+    amr::LevelC& L = m.lv[l];
+    L.n = f.n[l];
+    L.full = L.n + 2 * amr::kNG;
+    L.np = f.np[l];
+    L.cells = c.base_cells << l;
+    L.pid_base = f.pid_base[l];
+    L.cap = f.cap[l];
+    L.map_off = f.map_off[l];
+    L.ratio = f.ratio[l];
+    const long long box = ipow(L.full, c.dim);
+    L.pool_off = pool;
+    L.stride = box * m.nvar;
+    L.fr_off = frp;
+    L.fr_stride = 2LL * c.dim * m.nvar * ipow(L.n, c.dim - 1);
+    L.tag_off = tg;
+    L.h = (c.hi - c.lo) / (double)L.cells;
+    L.inv_h = 1.0 / L.h;
+    pool += L.stride * L.cap;
+    frp += L.fr_stride * L.cap;
+    tg += box * L.cap;
+  }
+  h->state_doubles = pool;
+  h->fr_doubles = frp;
+  h->tag_bytes = tg;
+}
+
+// Rebuild work lists on the host and upload them (plus the changed table
+// entries) to the device.
+void sync_tables(amr_hierarchy* h, bool full) {
+  amr::Forest& f = h->forest;
+  const int mp = f.max_patches;
+  // table deltas
+  std::vector<int> pairs;
+  auto push_pid = [&](int pid) {
+    pairs.push_back((int)(h->off_level + pid));
+    pairs.push_back(f.level[pid]);
+    pairs.push_back((int)(h->off_parent + pid));
+    pairs.push_back(f.parent[pid]);
+    pairs.push_back((int)(h->off_nchild + pid));
+    pairs.push_back(f.nchild[pid]);
+    for (int j = 0; j < 3; ++j) {
+      pairs.push_back((int)(h->off_coord + 3LL * pid + j));
+      pairs.push_back(f.coord[3 * pid + j]);
+    }
+    for (int k = 0; k < f.maxc; ++k) {
+      pairs.push_back((int)(h->off_child + (long long)pid * f.maxc + k));
+      pairs.push_back(f.child[(size_t)pid * f.maxc + k]);
+    }
+  };
+  if (full) {
+    std::vector<int> tab(h->tab_ints);
+    std::copy(f.level.begin(), f.level.end(), tab.begin() + h->off_level);
+    std::copy(f.parent.begin(), f.parent.end(), tab.begin() + h->off_parent);
+    std::copy(f.nchild.begin(), f.nchild.end(), tab.begin() + h->off_nchild);
+    std::copy(f.coord.begin(), f.coord.end(), tab.begin() + h->off_coord);
+    std::copy(f.child.begin(), f.child.end(), tab.begin() + h->off_child);
+    std::copy(f.map.begin(), f.map.end(), tab.begin() + h->off_map);
+    HIP_OK(hipMemcpyAsync(h->d_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
+    h->sync();
+  } else {
+    std::vector<uint8_t> dirty(mp, 0);
+    for (int mi : f.map_dirty) {
+      pairs.push_back((int)(h->off_map + mi));
+      pairs.push_back(f.map[mi]);
+    }
+    for (int q : f.touched) dirty[q] = 1;
+    for (int pid = 0; pid < mp; ++pid)
+      if (dirty[pid]) push_pid(pid);
+  }
+  f.map_dirty.clear();
+  f.touched.clear();
+
+  // active/leaf flags
+  h->h_active_leaf.assign(mp, 0);
+  for (int pid = 0; pid < mp; ++pid)
+    if (f.active[pid]) h->h_active_leaf[pid] = f.nchild[pid] ? 2 : 1;
+
+  // work lists
+  std::vector<int>& L = h->lists;
+  L.clear();
+  const std::vector<int> order = f.sorted_active();
+  auto begin_list = [&]() { return (int)L.size(); };
+  int a0 = begin_list();
+  for (int pid : order) L.push_back(pid);
+  const int a1 = begin_list();
+  for (int pid : order)
+    if (f.is_leaf(pid)) L.push_back(pid);
+  const int t0 = begin_list();
+  h->leaf_cells = 0;
+  for (int pid : order) {
+    if (!f.is_leaf(pid)) continue;
+    h->leaf_cells += ipow(f.n[f.level[pid]], f.dim);
+    const int nt = Kernels::tiles_per_patch(f.dim, h->dm.tile, f.n[f.level[pid]]);
+    for (int t = 0; t < nt; ++t) {
+      L.push_back(pid);
+      L.push_back(t);
+    }
+  }
+  const int r0 = begin_list();
+  int nref = 0;
+  for (int pid : order) {
+    if (!f.is_leaf(pid) || f.level[pid] + 1 >= f.nlev) continue;
+    const int l = f.level[pid];
+    const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
+    int mask = 0;
+    for (int j = 0; j < f.dim; ++j)
+      for (int side = 0; side < 2; ++side) {
+        int off[3] = {0, 0, 0}, q[3];
+        off[j] = side ? 1 : -1;
+        if (!f.shifted(l, c, off, q)) continue;
+        const int qp = f.lookup(l, q);
+        if (qp >= 0 && !f.is_leaf(qp)) mask |= 1 << (2 * j + side);
+      }
+    if (mask) {
+      L.push_back(pid);
+      L.push_back(mask);
+      ++nref;
+    }
+  }
+  int rs[amr::kMaxLev + 1] = {};
+  for (int l = 0; l < f.nlev; ++l) {
+    rs[l] = begin_list();
+    if (l == 0) continue;
+    for (int pid : order)
+      if (f.level[pid] == l) L.push_back(pid);
+  }
+  rs[f.nlev] = begin_list();
+  int ns[amr::kMaxLev + 1] = {};
+  for (int l = 0; l < f.nlev; ++l) {
+    ns[l] = begin_list();
+    for (int q : h->last_created)
+      if (f.level[q] == l) L.push_back(q);
+  }
+  ns[f.nlev] = begin_list();
+  if ((long long)L.size() > h->lists_cap) throw StateError("work-list buffer too small");
+  if (!L.empty())
+    HIP_OK(hipMemcpyAsync(h->d_lists, L.data(), L.size() * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
+  h->all = {h->d_lists + a0, a1 - a0};
+  h->leaves = {h->d_lists + a1, t0 - a1};
+  h->tiles = {h->d_lists + t0, (r0 - t0) / 2};
+  h->reflux = {h->d_lists + r0, nref};
+  for (int l = 0; l < f.nlev; ++l) {
+    h->restr[l] = {h->d_lists + rs[l], rs[l + 1] - rs[l]};
+    h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
+  }
+  HIP_OK(hipMemcpyAsync(h->d_active_leaf, h->h_active_leaf.data(), mp, hipMemcpyHostToDevice,
+                        h->stream));
+  if (!pairs.empty()) {
+    const long long np = (long long)pairs.size() / 2;
+    if (np > h->pairs_cap) throw StateError("table update buffer too small");
+    HIP_OK(hipMemcpyAsync(h->d_pairs, pairs.data(), pairs.size() * sizeof(int),
+                          hipMemcpyHostToDevice, h->stream));
+    Kernels::scatter_int(h->d_tab, h->d_pairs, (int)np, h->stream);
+    h->check_launch();
+  }
+  h->sync();  // host vectors above are reused by the next call
+}
+
+// Per-patch mode launches one kernel per list entry (the unfused baseline).
+template <typename F>
+void over_list(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F launch) {
+  if (h->exec_mode == AMR_EXEC_BATCHED) {
+    launch(lv.ptr, lv.count);
+  } else {
+    for (int i = 0; i < lv.count; ++i) launch(lv.ptr + (long long)i * stride_ints, 1);
+  }
+  h->check_launch();
+}
+
+void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv) {
+  over_list(h, lv, 1, [&](const int* p, int c) {
+    Kernels::fill(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+  });
+}
+
+void do_restrict(amr_hierarchy* h, int buf) {
+  for (int l = h->forest.nlev - 1; l >= 1; --l)
+    over_list(h, h->restr[l], 1, [&](const int* p, int c) {
+      Kernels::restrict_level(h->dm, h->U[buf], p, c, h->stream);
+    });
+}
+
+void do_stage(amr_hierarchy* h, int stage, const double* dt) {
+  static const int src[4] = {0, 0, 1, 2};
+  static const int dst[4] = {0, 1, 2, 0};
+  static const double w[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
+  const int s = src[stage], d = dst[stage];
+  do_fill(h, s, h->leaves);
+  const int tcells = ipow(h->dm.tile, h->cfg.dim);
+  over_list(h, h->tiles, 2, [&](const int* p, int c) {
+    hipEvent_t a{};
+    if (h->profiling) h->prof_begin(&a);
+    Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->stream);
+    if (h->profiling) h->prof_end((long long)c * tcells);
+  });
+  over_list(h, h->reflux, 2, [&](const int* p, int c) {
+    Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage], h->stream);
+  });
+  do_restrict(h, d);
+}
+
+void do_dt(amr_hierarchy* h, int buf, double* dt) {
+  Kernels::zero_u64(h->d_lam, h->stream);
+  over_list(h, h->leaves, 1, [&](const int* p, int c) {
+    Kernels::max_rate(h->dm, h->U[buf], p, c, h->d_lam, h->stream);
+  });
+  Kernels::dt_from_rate(h->dm, h->d_lam, dt, h->stream);
+  h->check_launch();
+}
+
+void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_t* cells) {
+  do_fill(h, buf, h->leaves);
+  over_list(h, h->leaves, 1, [&](const int* p, int c) {
+    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, cells ? h->d_raw : nullptr, h->stream);
+  });
+  if (cells)
+    over_list(h, h->leaves, 1, [&](const int* p, int c) {
+      Kernels::cell_tags(h->dm, h->d_raw, p, c, cells, h->stream);
+    });
+  Kernels::requests(h->dm, h->d_has_tag, h->d_active_leaf, h->forest.max_patches, refine, coarsen,
+                    h->stream);
+  h->check_launch();
+}
+
+int read_flag(amr_hierarchy* h, int idx) {
+  int v = 0;
+  HIP_OK(hipMemcpyAsync(&v, h->d_flags + idx, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  h->sync();
+  return v;
+}
+
+void clear_flags(amr_hierarchy* h) {
+  HIP_OK(hipMemsetAsync(h->d_flags, 0, 4 * sizeof(int), h->stream));
+}
+
+amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* coarsen,
+                       int* ncreated, int* ndeleted) {
+  std::vector<int> created, deleted;
+  try {
+    h->forest.regrid(refine, coarsen, created, deleted);
+  } catch (const amr::CapacityError& e) {
+    h->err = e.what();
+    return AMR_E_CAPACITY;
+  }
+  const std::string why = h->forest.validate();
+  if (!why.empty()) {
+    h->err = why;
+    return AMR_E_MESH;
+  }
+  h->last_created = created;
+  sync_tables(h, false);
+  clear_flags(h);
+  for (int l = 1; l < h->forest.nlev; ++l)
+    over_list(h, h->fresh[l], 1, [&](const int* p, int c) {
+      Kernels::prolong_new(h->dm, h->U[0], p, c, h->d_flags, h->stream);
+    });
+  if (read_flag(h, 0)) {
+    h->err = "prolongation source missing for a new patch";
+    return AMR_E_MESH;
+  }
+  if (ncreated) *ncreated = (int)created.size();
+  if (ndeleted) *ndeleted = (int)deleted.size();
+  return AMR_OK;
+}
+
+template <typename F>
+amr_status guarded(amr_hierarchy* h, F body) {
+  try {
+    return body();
+  } catch (const ArgError& e) {
+    if (h) h->err = e.what();
+    return AMR_E_ARG;
+  } catch (const HipError& e) {
+    if (h) h->err = e.what();
+    return AMR_E_HIP;
+  } catch (const amr::CapacityError& e) {
+    if (h) h->err = e.what();
+    return AMR_E_CAPACITY;
+  } catch (const amr::MeshError& e) {
+    if (h) h->err = e.what();
+    return AMR_E_MESH;
+  } catch (const StateError& e) {
+    if (h) h->err = e.what();
+    return AMR_E_STATE;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    return AMR_E_ARG;
+  }
+}
+
+int buf_ok(int buf) { return buf >= 0 && buf < 3; }
+
+}  // namespace
+
+extern "C" {
+
+amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* alloc,
+                                void* hip_stream, amr_hierarchy** out) {
+  if (!cfg || !out) return AMR_E_ARG;
+  *out = nullptr;
+  amr_hierarchy* h = new amr_hierarchy();
+  const amr_status st = guarded(h, [&]() -> amr_status {
+    validate_config(*cfg);
+    h->cfg = *cfg;
+    h->stream = (hipStream_t)hip_stream;
+    if (alloc && alloc->alloc && alloc->free) {
+      h->alloc = *alloc;
+      h->has_alloc = true;
+    }
+    h->exec_mode = cfg->exec_mode == AMR_EXEC_PER_PATCH ? AMR_EXEC_PER_PATCH : AMR_EXEC_BATCHED;
+    try {
+      h->forest.init(*cfg);
+    } catch (const std::invalid_argument& e) {
+      throw ArgError(e.what());
+    }
+    h->nvar = cfg->dim + 2;
+    build_devmesh(h);
+    amr::Forest& f = h->forest;
+    const long long mp = f.max_patches;
+    h->off_level = 0;
+    h->off_parent = mp;
+    h->off_nchild = 2 * mp;
+    h->off_coord = 3 * mp;
+    h->off_child = 6 * mp;
+    h->off_map = h->off_child + mp * f.maxc;
+    h->tab_ints = h->off_map + (long long)f.map.size();
+    if (h->tab_ints > 0x7fffffffLL) throw ArgError("patch tables exceed 2^31 entries");
+    for (int b = 0; b < 3; ++b) {
+      h->U[b] = (double*)h->dev_alloc(h->state_doubles * sizeof(double));
+      HIP_OK(hipMemsetAsync(h->U[b], 0, h->state_doubles * sizeof(double), h->stream));
+    }
+    h->fr = (double*)h->dev_alloc(h->fr_doubles * sizeof(double));
+    h->d_tab = (int*)h->dev_alloc(h->tab_ints * sizeof(int));
+    h->d_active_leaf = (uint8_t*)h->dev_alloc(mp);
+    h->d_has_tag = (uint8_t*)h->dev_alloc(mp);
+    h->d_refine = (uint8_t*)h->dev_alloc(mp);
+    h->d_coarsen = (uint8_t*)h->dev_alloc(mp);
+    h->d_raw = (uint8_t*)h->dev_alloc(h->tag_bytes);
+    h->d_lam = (unsigned long long*)h->dev_alloc(64);
+    h->d_dt = (double*)h->dev_alloc(64);
+    h->d_flags = (int*)h->dev_alloc(64);
+    long long tiles = 0;
+    for (int l = 0; l < f.nlev; ++l)
+      tiles += (long long)f.cap[l] * Kernels::tiles_per_patch(cfg->dim, h->dm.tile, f.n[l]);
+    h->lists_cap = 2 * tiles + 8 * mp + 64;
+    h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
+    h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
+    h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
+    h->d_pairs = (int*)h->dev_alloc(h->pairs_cap * 2 * sizeof(int));
+    HIP_OK(hipMemsetAsync(h->d_has_tag, 0, mp, h->stream));
+    HIP_OK(hipMemsetAsync(h->fr, 0, h->fr_doubles * sizeof(double), h->stream));
+    amr::DevMesh& m = h->dm;
+    m.level = h->d_tab + h->off_level;
+    m.parent = h->d_tab + h->off_parent;
+    m.nchild = h->d_tab + h->off_nchild;
+    m.coord = h->d_tab + h->off_coord;
+    m.child = h->d_tab + h->off_child;
+    m.map = h->d_tab + h->off_map;
+    sync_tables(h, true);
+    clear_flags(h);
+    h->sync();
+    return AMR_OK;
+  });
+  if (st != AMR_OK) {
+    // keep the message reachable through a minimal object
+    h->release_all();
+    *out = h;
+    return st;
+  }
+  *out = h;
+  return AMR_OK;
+}
+
+amr_status amr_destroy_hierarchy(amr_hierarchy* h) {
+  if (!h) return AMR_E_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  h->release_all();
+  delete h;
+  return AMR_OK;
+}
+
+const char* amr_last_error(const amr_hierarchy* h) { return h ? h->err.c_str() : "null hierarchy"; }
+
+amr_status amr_num_patches(const amr_hierarchy* h, int* nactive, int* nleaf) {
+  if (!h) return AMR_E_ARG;
+  if (nactive) *nactive = h->forest.count_active();
+  if (nleaf) *nleaf = h->forest.count_leaves();
+  return AMR_OK;
+}
+
+amr_status amr_patch_doubles(const amr_hierarchy* h, int level, int64_t* n) {
+  if (!h || !n || level < 0 || level >= h->cfg.max_levels) return AMR_E_ARG;
+  *n = h->dm.lv[level].stride;
+  return AMR_OK;
+}
+
+amr_status amr_state_doubles(const amr_hierarchy* h, int64_t* n) {
+  if (!h || !n) return AMR_E_ARG;
+  *n = h->state_doubles;
+  return AMR_OK;
+}
+
+amr_status amr_patch_offset(const amr_hierarchy* h, int pid, int64_t* off) {
+  if (!h || !off || pid < 0 || pid >= h->forest.max_patches || !h->forest.active[pid])
+    return AMR_E_ARG;
+  const amr::LevelC& L = h->dm.lv[h->forest.level[pid]];
+  *off = L.pool_off + (long long)(pid - L.pid_base) * L.stride;
+  return AMR_OK;
+}
+
+amr_status amr_state_ptr(const amr_hierarchy* h, int buf, double** dev) {
+  if (!h || !dev || !buf_ok(buf)) return AMR_E_ARG;
+  *dev = h->U[buf];
+  return AMR_OK;
+}
+
+amr_status amr_get_patch_table(const amr_hierarchy* h, amr_patch_info* out, int cap, int* n) {
+  if (!h || !n) return AMR_E_ARG;
+  const amr::Forest& f = h->forest;
+  const std::vector<int> order = f.sorted_active();
+  *n = (int)order.size();
+  for (int i = 0; i < (int)order.size() && i < cap && out; ++i) {
+    const int pid = order[i];
+    amr_patch_info& r = out[i];
+    std::memset(&r, 0, sizeof(r));
+    r.pid = pid;
+    r.level = f.level[pid];
+    for (int j = 0; j < 3; ++j) r.coord[j] = f.coord[3 * pid + j];
+    r.parent = f.parent[pid];
+    r.nchildren = f.nchild[pid];
+    int first = -1;
+    for (int k = 0; k < f.nchild[pid]; ++k) {
+      const int c = f.child[(size_t)pid * f.maxc + k];
+      if (first < 0 || c < first) first = c;
+    }
+    r.first_child = first;
+    for (int k = 0; k < 26; ++k) r.nbr[k] = -1;
+    int k = 0;
+    for (const auto& off : f.moore()) {
+      int q[3];
+      r.nbr[k++] = f.shifted(r.level, r.coord, off.data(), q) ? f.lookup(r.level, q) : -1;
+    }
+  }
+  return AMR_OK;
+}
+
+amr_status amr_set_state(amr_hierarchy* h, int buf, const double* host, const int* pids,
+                         int npatch) {
+  if (!h || !buf_ok(buf) || (npatch > 0 && (!host || !pids))) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    long long pos = 0;
+    for (int i = 0; i < npatch; ++i) {
+      int64_t off;
+      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
+      const long long cnt = h->dm.lv[h->forest.level[pids[i]]].stride;
+      HIP_OK(hipMemcpyAsync(h->U[buf] + off, host + pos, cnt * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+      pos += cnt;
+    }
+    h->sync();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_get_state(const amr_hierarchy* hc, int buf, double* host, const int* pids,
+                         int npatch) {
+  amr_hierarchy* h = const_cast<amr_hierarchy*>(hc);
+  if (!h || !buf_ok(buf) || (npatch > 0 && (!host || !pids))) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    long long pos = 0;
+    for (int i = 0; i < npatch; ++i) {
+      int64_t off;
+      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
+      const long long cnt = h->dm.lv[h->forest.level[pids[i]]].stride;
+      HIP_OK(hipMemcpyAsync(host + pos, h->U[buf] + off, cnt * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+      pos += cnt;
+    }
+    h->sync();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* prim, const int* pids,
+                              int npatch) {
+  if (!h || !buf_ok(buf) || (npatch > 0 && (!prim || !pids))) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    const int d = h->cfg.dim, nv = h->nvar;
+    const double gm1 = h->cfg.gamma - 1.0;
+    long long pos = 0;
+    for (int i = 0; i < npatch; ++i) {
+      int64_t off;
+      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
+      const amr::LevelC& L = h->dm.lv[h->forest.level[pids[i]]];
+      const long long cells = ipow(L.n, d);
+      const long long box = ipow(L.full, d);
+      std::vector<double> patch(L.stride);
+      HIP_OK(hipMemcpyAsync(patch.data(), h->U[buf] + off, L.stride * sizeof(double),
+                            hipMemcpyDeviceToHost, h->stream));
+      h->sync();
+      for (long long c = 0; c < cells; ++c) {
+        const int x = (int)(c % L.n);
+        const int y = d >= 2 ? (int)((c / L.n) % L.n) : 0;
+        const int z = d >= 3 ? (int)(c / ((long long)L.n * L.n)) : 0;
+        long long b = x + amr::kNG;
+        if (d >= 2) b += (long long)(y + amr::kNG) * L.full;
+        if (d >= 3) b += (long long)(z + amr::kNG) * L.full * L.full;
+        const double rho = prim[pos + c];
+        double uu = 0.0;
+        for (int j = 0; j < d; ++j) {
+          const double u = prim[pos + (1 + j) * cells + c];
+          uu = (j == 0) ? u * u : uu + u * u;
+          patch[(1 + j) * box + b] = rho * u;
+        }
+        const double p = prim[pos + (d + 1) * cells + c];
+        patch[b] = rho;
+        patch[(nv - 1) * box + b] = p / gm1 + 0.5 * rho * uu;
+      }
+      HIP_OK(hipMemcpyAsync(h->U[buf] + off, patch.data(), L.stride * sizeof(double),
+                            hipMemcpyHostToDevice, h->stream));
+      h->sync();
+      pos += (long long)nv * cells;
+    }
+    return AMR_OK;
+  });
+}
+
+amr_status amr_fill_ghosts(amr_hierarchy* h, int buf) {
+  if (!h || !buf_ok(buf)) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_fill(h, buf, h->all);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
+  if (!h || !buf_ok(buf) || !rhs_dev) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_fill(h, buf, h->leaves);
+    over_list(h, h->tiles, 2, [&](const int* p, int c) {
+      Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, h->d_dt,
+                     h->stream);
+    });
+    over_list(h, h->reflux, 2, [&](const int* p, int c) {
+      Kernels::reflux(h->dm, amr::kModeRHS, rhs_dev, h->fr, p, c, h->d_dt, 1.0, h->stream);
+    });
+    return AMR_OK;
+  });
+}
+
+amr_status amr_compute_dt(amr_hierarchy* h, int buf, double* dt_dev) {
+  if (!h || !buf_ok(buf) || !dt_dev) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_dt(h, buf, dt_dev);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_rk_stage(amr_hierarchy* h, int stage, const double* dt_dev) {
+  if (!h || stage < 1 || stage > 3 || !dt_dev) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_stage(h, stage, dt_dev);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
+  if (!h) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    double* dt = dt_dev ? dt_dev : h->d_dt;
+    do_dt(h, 0, dt);
+    for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_tag(amr_hierarchy* h, int buf, uint8_t* refine_req_dev, uint8_t* coarsen_req_dev,
+                   uint8_t* cell_tags_dev) {
+  if (!h || !buf_ok(buf)) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_tag(h, buf, refine_req_dev, coarsen_req_dev, cell_tags_dev);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_regrid(amr_hierarchy* h, const uint8_t* refine_req_host,
+                      const uint8_t* coarsen_req_host, int* ncreated, int* ndeleted) {
+  if (!h) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    h->sync();
+    return regrid_impl(h, refine_req_host, coarsen_req_host, ncreated, ndeleted);
+  });
+}
+
+amr_status amr_adapt(amr_hierarchy* h, int* ncreated, int* ndeleted) {
+  if (!h) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    const int mp = h->forest.max_patches;
+    do_tag(h, 0, h->d_refine, h->d_coarsen, nullptr);
+    std::vector<uint8_t> rq(mp), cq(mp);
+    HIP_OK(hipMemcpyAsync(rq.data(), h->d_refine, mp, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(cq.data(), h->d_coarsen, mp, hipMemcpyDeviceToHost, h->stream));
+    h->sync();
+    return regrid_impl(h, rq.data(), cq.data(), ncreated, ndeleted);
+  });
+}
+
+amr_status amr_check(amr_hierarchy* h, int* nonphysical_count) {
+  if (!h) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    clear_flags(h);
+    over_list(h, h->leaves, 1, [&](const int* p, int c) {
+      Kernels::check(h->dm, h->U[0], p, c, h->d_flags + 1, h->stream);
+    });
+    const int bad = read_flag(h, 1);
+    if (nonphysical_count) *nonphysical_count = bad;
+    if (bad) {
+      h->err = "non-physical leaf cells (rho <= 0, p <= 0 or NaN)";
+      return AMR_E_NONPHYSICAL;
+    }
+    return AMR_OK;
+  });
+}
+
+amr_status amr_set_exec_mode(amr_hierarchy* h, int mode) {
+  if (!h || (mode != AMR_EXEC_PER_PATCH && mode != AMR_EXEC_BATCHED)) return AMR_E_ARG;
+  h->exec_mode = mode;
+  return AMR_OK;
+}
+
+amr_status amr_last_created(const amr_hierarchy* h, int* pids, int cap, int* n) {
+  if (!h || !n) return AMR_E_ARG;
+  *n = (int)h->last_created.size();
+  for (int i = 0; i < *n && i < cap && pids; ++i) pids[i] = h->last_created[i];
+  return AMR_OK;
+}
+
+amr_status amr_fill_error(amr_hierarchy* h, int* flag) {
+  if (!h || !flag) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    *flag = read_flag(h, 0);
+    return AMR_OK;
+  });
+}
+
+amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq,
+                             amr_patch_info* out, int cap, int* n) {
+  if (!cfg || !n || (nreq > 0 && !req)) return AMR_E_ARG;
+  try {
+    validate_config(*cfg);
+    amr::Forest f;
+    f.init(*cfg);
+    const int mp = f.max_patches;
+    std::vector<uint8_t> rq(mp), cq(mp);
+    int i = 0;
+    while (i < nreq) {
+      const int round = req[6 * i];
+      std::fill(rq.begin(), rq.end(), 0);
+      std::fill(cq.begin(), cq.end(), 0);
+      for (; i < nreq && req[6 * i] == round; ++i) {
+        const int32_t* r = req + 6 * i;
+        const int l = r[2];
+        if (l < 0 || l >= f.nlev) return AMR_E_ARG;
+        const int c[3] = {r[3], r[4], r[5]};
+        for (int j = 0; j < f.dim; ++j)
+          if (c[j] < 0 || c[j] >= f.np[l]) return AMR_E_ARG;
+        const int pid = f.lookup(l, c);
+        if (pid < 0) continue;
+        (r[1] ? cq : rq)[pid] = 1;
+      }
+      std::vector<int> created, deleted;
+      f.regrid(rq.data(), cq.data(), created, deleted);
+      if (!f.validate().empty()) return AMR_E_MESH;
+    }
+    const std::vector<int> order = f.sorted_active();
+    *n = (int)order.size();
+    for (int k = 0; k < (int)order.size() && k < cap && out; ++k) {
+      const int pid = order[k];
+      amr_patch_info& r = out[k];
+      std::memset(&r, 0, sizeof(r));
+      r.pid = pid;
+      r.level = f.level[pid];
+      for (int j = 0; j < 3; ++j) r.coord[j] = f.coord[3 * pid + j];
+      r.parent = f.parent[pid];
+      r.nchildren = f.nchild[pid];
+      r.first_child = f.nchild[pid] ? f.child[(size_t)pid * f.maxc] : -1;
+      for (int q = 0; q < 26; ++q) r.nbr[q] = -1;
+    }
+    return AMR_OK;
+  } catch (const amr::CapacityError&) {
+    return AMR_E_CAPACITY;
+  } catch (const std::exception&) {
+    return AMR_E_ARG;
+  }
+}
+
+amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells) {
+  if (!h || !cells) return AMR_E_ARG;
+  *cells = h->leaf_cells;
+  return AMR_OK;
+}
+
+amr_status amr_profile(amr_hierarchy* h, int enable) {
+  if (!h) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    h->sync();
+    h->profiling = enable != 0;
+    h->ev_used = 0;
+    h->ev_cells.clear();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, int64_t* cells) {
+  if (!h || !total_ms || !launches || !cells) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    h->sync();
+    double ms = 0.0;
+    long long c = 0;
+    for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+      float e = 0.f;
+      HIP_OK(hipEventElapsedTime(&e, h->ev_pool[i], h->ev_pool[i + 1]));
+      ms += e;
+    }
+    for (long long v : h->ev_cells) c += v;
+    *total_ms = ms;
+    *launches = (int)h->ev_cells.size();
+    *cells = c;
+    return AMR_OK;
+  });
+}
+
+}  // extern "C"

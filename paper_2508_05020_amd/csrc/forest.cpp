@@ -1,0 +1,320 @@
+#include <algorithm>
+#include <array>
+#include <sstream>
+
+#include "forest.hpp"
+
+namespace amr {
+
+void Forest::init(const amr_config& cfg) {
+  dim = cfg.dim;
+  nlev = cfg.max_levels;
+  max_patches = cfg.max_patches;
+  coarsen_rule = cfg.coarsen_rule;
+  for (int j = 0; j < 3; ++j) periodic[j] = j < dim ? cfg.periodic[j] : 1;
+  maxc = 1;
+  long long mapsize = 0;
+  for (int l = 0; l < nlev; ++l) {
+    n[l] = cfg.patch_cells[l];
+    np[l] = (cfg.base_cells << l) / n[l];
+    ratio[l] = (l + 1 < nlev) ? 2 * n[l] / cfg.patch_cells[l + 1] : 0;
+    int c = 1;
+    for (int j = 0; j < dim; ++j) c *= ratio[l];
+    if (l + 1 < nlev) maxc = std::max(maxc, c);
+    map_off[l] = (int)mapsize;
+    long long m = 1;
+    for (int j = 0; j < dim; ++j) m *= np[l];
+    mapsize += m;
+  }
+  // slot ranges: explicit capacities, else level 0 exact and the rest of
+  // max_patches shared equally by the finer levels (capped by level size)
+  long long used = 0;
+  long long l0 = 1;
+  for (int j = 0; j < dim; ++j) l0 *= np[0];
+  for (int l = 0; l < nlev; ++l) {
+    long long full = 1;
+    for (int j = 0; j < dim; ++j) full *= np[l];
+    long long c = cfg.level_capacity[l];
+    if (c <= 0) {
+      if (l == 0) c = l0;
+      else c = std::max<long long>(1, (max_patches - l0) / std::max(1, nlev - 1));
+    }
+    c = std::min(c, full);
+    pid_base[l] = (int)used;
+    cap[l] = (int)c;
+    used += c;
+  }
+  if (used > max_patches) throw std::invalid_argument("level capacities exceed max_patches");
+  if (cap[0] < l0) throw std::invalid_argument("max_patches below the level-0 patch count");
+
+  level.assign(max_patches, -1);
+  parent.assign(max_patches, -1);
+  nchild.assign(max_patches, 0);
+  child.assign((size_t)max_patches * maxc, -1);
+  coord.assign((size_t)max_patches * 3, 0);
+  active.assign(max_patches, 0);
+  map.assign(mapsize, -1);
+  map_dirty.clear();
+  touched.clear();
+  free_.assign(nlev, {});
+  for (int l = 0; l < nlev; ++l)
+    for (int s = 0; s < cap[l]; ++s) free_[l].insert(pid_base[l] + s);
+
+  moore_.clear();
+  const int rz = dim >= 3 ? 1 : 0, ry = dim >= 2 ? 1 : 0;
+  for (int dz = -rz; dz <= rz; ++dz)
+    for (int dy = -ry; dy <= ry; ++dy)
+      for (int dx = -1; dx <= 1; ++dx)
+        if (dx || dy || dz) moore_.push_back({dx, dy, dz});
+
+  const int m0 = np[0];
+  for (int z = 0; z < (dim >= 3 ? m0 : 1); ++z)
+    for (int y = 0; y < (dim >= 2 ? m0 : 1); ++y)
+      for (int x = 0; x < m0; ++x) {
+        const int c[3] = {x, y, z};
+        alloc(0, c, -1);
+      }
+}
+
+int Forest::map_index(int l, const int c[3]) const {
+  int idx = c[0];
+  if (dim >= 2) idx += np[l] * c[1];
+  if (dim >= 3) idx += np[l] * np[l] * c[2];
+  return map_off[l] + idx;
+}
+
+bool Forest::shifted(int l, const int c[3], const int off[3], int out[3]) const {
+  out[0] = out[1] = out[2] = 0;
+  for (int j = 0; j < dim; ++j) {
+    int v = c[j] + off[j];
+    if (v < 0 || v >= np[l]) {
+      if (!periodic[j]) return false;
+      v = ((v % np[l]) + np[l]) % np[l];
+    }
+    out[j] = v;
+  }
+  return true;
+}
+
+void Forest::covering(int l, const int c[3], int out[3]) const {
+  out[0] = out[1] = out[2] = 0;
+  for (int j = 0; j < dim; ++j) out[j] = (c[j] * n[l] / 2) / n[l - 1];
+}
+
+int Forest::alloc(int l, const int c[3], int par) {
+  if (free_[l].empty()) return -1;
+  const int pid = *free_[l].begin();
+  free_[l].erase(free_[l].begin());
+  level[pid] = l;
+  parent[pid] = par;
+  nchild[pid] = 0;
+  active[pid] = 1;
+  for (int j = 0; j < 3; ++j) coord[3 * pid + j] = c[j];
+  const int mi = map_index(l, c);
+  map[mi] = pid;
+  map_dirty.push_back(mi);
+  touched.push_back(pid);
+  if (par >= 0) touched.push_back(par);
+  return pid;
+}
+
+void Forest::release(int pid) {
+  const int l = level[pid];
+  const int c[3] = {coord[3 * pid], coord[3 * pid + 1], coord[3 * pid + 2]};
+  const int mi = map_index(l, c);
+  map[mi] = -1;
+  map_dirty.push_back(mi);
+  touched.push_back(pid);
+  if (parent[pid] >= 0) touched.push_back(parent[pid]);
+  active[pid] = 0;
+  level[pid] = -1;
+  parent[pid] = -1;
+  nchild[pid] = 0;
+  free_[l].insert(pid);
+}
+
+// Algorithm 1: a leaf p first makes each absent Moore neighbour q exist by
+// refining the level l-1 patch that covers q (recursively), then receives its
+// children.  Positions outside a non-periodic domain count as present.
+void Forest::refine(int pid, std::vector<int>& created) {
+  if (!active[pid]) throw MeshError("refinement of an inactive patch");
+  if (!is_leaf(pid)) return;
+  const int l = level[pid];
+  if (l + 1 >= nlev) throw MeshError("refinement beyond the finest level");
+  const int c[3] = {coord[3 * pid], coord[3 * pid + 1], coord[3 * pid + 2]};
+  for (const auto& off : moore_) {
+    int q[3];
+    if (!shifted(l, c, off.data(), q)) continue;
+    if (lookup(l, q) >= 0) continue;
+    if (l == 0) throw MeshError("missing level-0 patch");
+    int r[3];
+    covering(l, q, r);
+    const int rp = lookup(l - 1, r);
+    if (rp < 0) throw MeshError("covering patch of a missing neighbour is absent");
+    refine(rp, created);
+  }
+  const int rr = ratio[l];
+  const int rz = dim >= 3 ? rr : 1, ry = dim >= 2 ? rr : 1;
+  int k = 0;
+  for (int oz = 0; oz < rz; ++oz)
+    for (int oy = 0; oy < ry; ++oy)
+      for (int ox = 0; ox < rr; ++ox) {
+        int cc[3] = {c[0] * rr + ox, dim >= 2 ? c[1] * rr + oy : 0, dim >= 3 ? c[2] * rr + oz : 0};
+        const int q = alloc(l + 1, cc, pid);
+        if (q < 0) throw CapacityError("patch pool of a level exhausted");
+        child[(size_t)pid * maxc + k] = q;
+        nchild[pid] = ++k;
+        created.push_back(q);
+      }
+}
+
+// Algorithm 2, text reading: P needs children, all of them leaves, and none
+// of them may be a Moore neighbour of a same-level patch that has children.
+// The literal rule instead refuses level 0 and any P with a Moore neighbour
+// that has children.
+bool Forest::coarsening_allowed(int pid) const {
+  if (!active[pid] || is_leaf(pid)) return false;
+  const int l = level[pid];
+  for (int k = 0; k < nchild[pid]; ++k)
+    if (!is_leaf(child[(size_t)pid * maxc + k])) return false;
+  if (coarsen_rule == AMR_COARSEN_LITERAL) {
+    if (l == 0) return false;
+    const int c[3] = {coord[3 * pid], coord[3 * pid + 1], coord[3 * pid + 2]};
+    for (const auto& off : moore_) {
+      int q[3];
+      if (!shifted(l, c, off.data(), q)) continue;
+      const int qp = lookup(l, q);
+      if (qp >= 0 && !is_leaf(qp)) return false;
+    }
+    return true;
+  }
+  for (int k = 0; k < nchild[pid]; ++k) {
+    const int ch = child[(size_t)pid * maxc + k];
+    const int c[3] = {coord[3 * ch], coord[3 * ch + 1], coord[3 * ch + 2]};
+    for (const auto& off : moore_) {
+      int q[3];
+      if (!shifted(l + 1, c, off.data(), q)) continue;
+      const int qp = lookup(l + 1, q);
+      if (qp < 0 || parent[qp] == pid) continue;
+      if (!is_leaf(qp)) return false;
+    }
+  }
+  return true;
+}
+
+void Forest::delete_children(int pid, std::vector<int>& deleted) {
+  for (int k = 0; k < nchild[pid]; ++k) {
+    const int ch = child[(size_t)pid * maxc + k];
+    deleted.push_back(ch);
+    release(ch);
+    child[(size_t)pid * maxc + k] = -1;
+  }
+  nchild[pid] = 0;
+}
+
+static bool order_less(const Forest& f, int a, int b) {
+  if (f.level[a] != f.level[b]) return f.level[a] < f.level[b];
+  for (int j = 2; j >= 0; --j)
+    if (f.coord[3 * a + j] != f.coord[3 * b + j]) return f.coord[3 * a + j] < f.coord[3 * b + j];
+  return a < b;
+}
+
+void Forest::regrid(const uint8_t* refine_req, const uint8_t* coarsen_req,
+                    std::vector<int>& created, std::vector<int>& deleted) {
+  std::vector<int> rq, cq;
+  for (int pid = 0; pid < max_patches; ++pid) {
+    if (!active[pid]) continue;
+    if (refine_req && refine_req[pid] && is_leaf(pid) && level[pid] + 1 < nlev) rq.push_back(pid);
+    if (coarsen_req && coarsen_req[pid] && !is_leaf(pid)) cq.push_back(pid);
+  }
+  std::sort(rq.begin(), rq.end(), [&](int a, int b) { return order_less(*this, a, b); });
+  try {
+    for (int pid : rq)
+      if (active[pid] && is_leaf(pid)) refine(pid, created);
+  } catch (const CapacityError&) {
+    // undo: remove every patch created in this pass, newest first
+    for (auto it = created.rbegin(); it != created.rend(); ++it) {
+      const int q = *it;
+      const int par = parent[q];
+      release(q);
+      if (par >= 0) {
+        nchild[par] = 0;
+        for (int k = 0; k < maxc; ++k) child[(size_t)par * maxc + k] = -1;
+      }
+    }
+    created.clear();
+    throw;
+  }
+  std::vector<uint8_t> fresh_parent(max_patches, 0);
+  for (int q : created) fresh_parent[parent[q]] = 1;
+  std::sort(cq.begin(), cq.end(), [&](int a, int b) {
+    if (level[a] != level[b]) return level[a] > level[b];
+    return order_less(*this, a, b);
+  });
+  for (int pid : cq) {
+    if (!active[pid] || fresh_parent[pid]) continue;
+    if (coarsening_allowed(pid)) delete_children(pid, deleted);
+  }
+}
+
+std::string Forest::validate() const {
+  std::ostringstream why;
+  const int m0 = np[0];
+  for (int z = 0; z < (dim >= 3 ? m0 : 1); ++z)
+    for (int y = 0; y < (dim >= 2 ? m0 : 1); ++y)
+      for (int x = 0; x < m0; ++x) {
+        const int c[3] = {x, y, z};
+        if (lookup(0, c) < 0) return "R1: a level-0 patch is missing";
+      }
+  for (int pid = 0; pid < max_patches; ++pid) {
+    if (!active[pid]) continue;
+    const int l = level[pid];
+    const int c[3] = {coord[3 * pid], coord[3 * pid + 1], coord[3 * pid + 2]};
+    if (lookup(l, c) != pid) return "patch map disagrees with the patch table";
+    if (l > 0) {
+      int r[3];
+      covering(l, c, r);
+      if (lookup(l - 1, r) != parent[pid]) return "parent link broken";
+    }
+    if (nchild[pid]) {
+      for (const auto& off : moore_) {
+        int q[3];
+        if (!shifted(l, c, off.data(), q)) continue;
+        if (lookup(l, q) < 0) {
+          why << "R2: patch " << pid << " has children but a Moore neighbour is absent";
+          return why.str();
+        }
+      }
+    }
+  }
+  return "";
+}
+
+int Forest::levels_in_use() const {
+  int m = 0;
+  for (int pid = 0; pid < max_patches; ++pid)
+    if (active[pid]) m = std::max(m, level[pid] + 1);
+  return m;
+}
+
+int Forest::count_active() const {
+  int c = 0;
+  for (int pid = 0; pid < max_patches; ++pid) c += active[pid] ? 1 : 0;
+  return c;
+}
+
+int Forest::count_leaves() const {
+  int c = 0;
+  for (int pid = 0; pid < max_patches; ++pid) c += (active[pid] && nchild[pid] == 0) ? 1 : 0;
+  return c;
+}
+
+std::vector<int> Forest::sorted_active() const {
+  std::vector<int> out;
+  for (int pid = 0; pid < max_patches; ++pid)
+    if (active[pid]) out.push_back(pid);
+  std::sort(out.begin(), out.end(), [&](int a, int b) { return order_less(*this, a, b); });
+  return out;
+}
+
+}  // namespace amr

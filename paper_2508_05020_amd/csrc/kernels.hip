@@ -1,0 +1,964 @@
+// HIP kernels of libamr for gfx950 (CDNA4, wave64).
+//
+// Every kernel works on the patch pools described in amr_internal.hpp: a
+// patch of level l stores nvar * (n_l + 8)^dim doubles, var-major, x fastest,
+// with 4 ghost layers.  Work lists (pids or (pid, tile) pairs) are device
+// arrays built by the host after each regrid, so one launch covers the
+// patches of every level.
+//
+// Floating-point contract: the RHS/stage path may contract a*b+c into FMA
+// (its results are compared with the FP64 reference to a relative tolerance);
+// the prolongation, restriction, tag and time-step paths disable contraction
+// and use the same operation order as the definitions they implement, so
+// that integer decisions (tags, positivity switches) are taken on identical
+// values.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "amr_internal.hpp"
+
+namespace amr {
+namespace {
+
+constexpr int NG = kNG;
+
+__device__ __forceinline__ int bc_map(int g, int N, int periodic) {
+  if (periodic) {
+    g %= N;
+    return g < 0 ? g + N : g;
+  }
+  return g < 0 ? 0 : (g >= N ? N - 1 : g);
+}
+
+template <int D>
+__device__ __forceinline__ long long box_off(int full, int x, int y, int z) {
+  if constexpr (D == 1) return x;
+  if constexpr (D == 2) return (long long)y * full + x;
+  return ((long long)z * full + y) * full + x;
+}
+
+template <int D>
+__device__ __forceinline__ long long var_stride(int full) {
+  if constexpr (D == 1) return full;
+  if constexpr (D == 2) return (long long)full * full;
+  return (long long)full * full * full;
+}
+
+__device__ __forceinline__ long long patch_base(const DevMesh& m, int pid, int l) {
+  return m.lv[l].pool_off + (long long)(pid - m.lv[l].pid_base) * m.lv[l].stride;
+}
+
+template <int D>
+__device__ __forceinline__ int map_at(const DevMesh& m, int l, const int q[3]) {
+  const LevelC& L = m.lv[l];
+  int idx = q[0];
+  if constexpr (D >= 2) idx += L.np * q[1];
+  if constexpr (D >= 3) idx += L.np * L.np * q[2];
+  return m.map[L.map_off + idx];
+}
+
+// Conserved values of the level-l cell at in-domain global index g.
+template <int D>
+__device__ bool fetch_cell(const DevMesh& m, const double* __restrict__ U, int l,
+                           const int g[3], double out[D + 2]) {
+  const LevelC& L = m.lv[l];
+  int q[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+  for (int j = 0; j < D; ++j) {
+    q[j] = g[j] / L.n;
+    c[j] = g[j] - q[j] * L.n;
+  }
+  const int pid = map_at<D>(m, l, q);
+  if (pid < 0) return false;
+  const double* P = U + patch_base(m, pid, l);
+  const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+  const long long vs = var_stride<D>(L.full);
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) out[v] = P[v * vs + off];
+  return true;
+}
+
+// Pressure from conserved values in the reference operation order:
+// u_j = m_j / rho, ke = 0.5 * (m_x u_x + m_y u_y + m_z u_z), p = (gamma-1)(E - ke).
+template <int D>
+__device__ __forceinline__ double pressure_exact(const double* u, double gm1) {
+#pragma clang fp contract(off)
+  const double rho = u[0];
+  double ke = u[1] * (u[1] / rho);
+#pragma unroll
+  for (int j = 1; j < D; ++j) ke = ke + u[1 + j] * (u[1 + j] / rho);
+  ke = 0.5 * ke;
+  return gm1 * (u[D + 1] - ke);
+}
+
+// Conservative MC-limited linear prolongation of the level-lf cell at mapped
+// global index g from level lf-1.  Slopes are dropped when any of the 2^D
+// children of the coarse cell would have rho <= 0 or p <= 0.
+template <int D>
+__device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int lf,
+                             const int g[3], double out[D + 2]) {
+#pragma clang fp contract(off)
+  constexpr int NV = D + 2;
+  const int lc = lf - 1;
+  const LevelC& C = m.lv[lc];
+  int gc[3] = {0, 0, 0};
+  double sig[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < D; ++j) {
+    gc[j] = g[j] >> 1;
+    sig[j] = (g[j] & 1) ? 1.0 : -1.0;
+  }
+  double phi[NV];
+  if (!fetch_cell<D>(m, U, lc, gc, phi)) return false;
+  double s[D][NV];
+  for (int j = 0; j < D; ++j) {
+    int gp[3] = {gc[0], gc[1], gc[2]};
+    int gm[3] = {gc[0], gc[1], gc[2]};
+    gp[j] = bc_map(gc[j] + 1, C.cells, m.periodic[j]);
+    gm[j] = bc_map(gc[j] - 1, C.cells, m.periodic[j]);
+    double up[NV], dn[NV];
+    if (!fetch_cell<D>(m, U, lc, gp, up)) return false;
+    if (!fetch_cell<D>(m, U, lc, gm, dn)) return false;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double a = up[v] - phi[v];
+      const double b = phi[v] - dn[v];
+      const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+      const double mag = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
+      s[j][v] = same ? copysign(mag, a) : 0.0;
+    }
+  }
+  bool bad = false;
+  for (int c = 0; c < (1 << D); ++c) {
+    double ch[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double x = phi[v];
+      for (int j = 0; j < D; ++j) x = x + (((c >> j) & 1) ? 0.25 : -0.25) * s[j][v];
+      ch[v] = x;
+    }
+    const double p = pressure_exact<D>(ch, m.gm1);
+    if (!(ch[0] > 0.0 && p > 0.0)) bad = true;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double x = phi[v];
+    for (int j = 0; j < D; ++j) x = x + (sig[j] * 0.25) * (bad ? 0.0 : s[j][v]);
+    out[v] = x;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// ghost fill
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
+                                              const int* __restrict__ list, int count,
+                                              int* __restrict__ err) {
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[blockIdx.x];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, full = L.full;
+  const long long vs = var_stride<D>(full);
+  double* P = U + patch_base(m, pid, l);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  const int total = (int)vs;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int b[3] = {idx % full, 0, 0};
+    if constexpr (D >= 2) b[1] = (idx / full) % full;
+    if constexpr (D >= 3) b[2] = idx / (full * full);
+    bool ghost = false;
+    int g[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) {
+      const int c = b[j] - NG;
+      ghost |= (c < 0) || (c >= n);
+      g[j] = bc_map(pc[j] * n + c, L.cells, m.periodic[j]);
+    }
+    if (!ghost) continue;
+    double val[NV];
+    bool ok = fetch_cell<D>(m, U, l, g, val);
+    if (!ok) ok = (l > 0) && prolong_cell<D>(m, U, l, g, val);
+    if (!ok) {
+      err[0] = 1;
+      for (int v = 0; v < NV; ++v) val[v] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[v * vs + idx] = val[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused right-hand side + SSP-RK3 stage on (pid, tile) work items
+// ---------------------------------------------------------------------------
+
+// WENO5-JS value at the edge between c and d (five nodes a..e).  The
+// nonlinear weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
+// t_k = (eps + beta_k)^2, are evaluated as cross products so that one
+// division serves all three weights.
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e,
+                                        double eps) {
+  const double q0 = (3.0 * a - 10.0 * b + 15.0 * c) * 0.125;
+  const double q1 = (-b + 6.0 * c + 3.0 * d) * 0.125;
+  const double q2 = (3.0 * c + 6.0 * d - e) * 0.125;
+  const double k0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
+  const double k1 = b - 2.0 * c + d, s1 = b - d;
+  const double k2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+  const double c1312 = 13.0 / 12.0;
+  const double b0 = c1312 * k0 * k0 + 0.25 * s0 * s0;
+  const double b1 = c1312 * k1 * k1 + 0.25 * s1 * s1;
+  const double b2 = c1312 * k2 * k2 + 0.25 * s2 * s2;
+  const double t0 = (eps + b0) * (eps + b0);
+  const double t1 = (eps + b1) * (eps + b1);
+  const double t2 = (eps + b2) * (eps + b2);
+  const double a0 = (1.0 / 16.0) * (t1 * t2);
+  const double a1 = (10.0 / 16.0) * (t0 * t2);
+  const double a2 = (5.0 / 16.0) * (t0 * t1);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+__device__ __forceinline__ double central4(double b, double c, double d, double e) {
+  return (9.0 * (c + d) - (b + e)) * 0.0625;
+}
+
+template <int D>
+struct EdgeState {
+  double p, T, u[D];
+};
+
+// Conserved state and direction-J flux of an edge state (Eq. (1)-(3), (5)-(7)).
+template <int D, int J>
+__device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& w,
+                                          double U[D + 2], double F[D + 2], double& speed) {
+  const double rho = w.p / w.T;
+  double uu = w.u[0] * w.u[0];
+#pragma unroll
+  for (int i = 1; i < D; ++i) uu += w.u[i] * w.u[i];
+  const double E = w.p * m.igm1 + 0.5 * rho * uu;
+  U[0] = rho;
+  F[0] = rho * w.u[J];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double mi = rho * w.u[i];
+    U[1 + i] = mi;
+    F[1 + i] = mi * w.u[J] + (i == J ? w.p : 0.0);
+  }
+  U[D + 1] = E;
+  F[D + 1] = (E + w.p) * w.u[J];
+  speed = sqrt(m.gamma * w.T) + fabs(w.u[J]);
+}
+
+template <int D, int TX, int TY, int TZ>
+struct TileShape {
+  static constexpr int T0 = TX;
+  static constexpr int T1 = D >= 2 ? TY : 1;
+  static constexpr int T2 = D >= 3 ? TZ : 1;
+  static constexpr int NCELL = T0 * T1 * T2;
+  static constexpr int ext(int j) {
+    return (T0 + (j == 0 ? 8 : 0)) * (T1 + (j == 1 ? 8 : 0)) * (T2 + (j == 2 ? 8 : 0));
+  }
+  static constexpr int edges(int j) {
+    return (T0 + (j == 0 ? 3 : 0)) * (T1 + (j == 1 ? 3 : 0)) * (T2 + (j == 2 ? 3 : 0));
+  }
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int EXTMAX = cmax(ext(0), cmax(D >= 2 ? ext(1) : 0, D >= 3 ? ext(2) : 0));
+  static constexpr int EDMAX =
+      cmax(edges(0), cmax(D >= 2 ? edges(1) : 0, D >= 3 ? edges(2) : 0));
+};
+
+template <int D, int TX, int TY, int TZ, int NT, int J>
+__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Pin,
+                                                double* __restrict__ frp, int n, int full,
+                                                const int o[3], double* sP, double* sF,
+                                                double acc[][D + 2], double inv_h) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int NQ = D + 2;  // interpolated primitives: p, T, u_j
+  constexpr int E0 = S::T0 + (J == 0 ? 8 : 0);
+  constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
+  constexpr int E2 = S::T2 + (J == 2 ? 8 : 0);
+  constexpr int NEXT = E0 * E1 * E2;
+  constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
+  constexpr int G1 = S::T1 + (J == 1 ? 3 : 0);
+  constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
+  constexpr int NED = G0 * G1 * G2;
+  constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
+  constexpr int CPT = (S::NCELL + NT - 1) / NT;
+  const long long vs = var_stride<D>(full);
+  const int tid = threadIdx.x;
+
+  // 1. primitives of the tile extended by 4 nodes on both sides along J
+  for (int idx = tid; idx < NEXT; idx += NT) {
+    const int e0 = idx % E0;
+    const int e1 = (idx / E0) % E1;
+    const int e2 = idx / (E0 * E1);
+    const int cx = o[0] + e0 - (J == 0 ? 4 : 0);
+    const int cy = o[1] + e1 - (J == 1 ? 4 : 0);
+    const int cz = o[2] + e2 - (J == 2 ? 4 : 0);
+    const long long off = box_off<D>(full, cx + NG, cy + NG, cz + NG);
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+    const double r = 1.0 / u[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double ui = u[1 + i] * r;
+      ke += u[1 + i] * ui;
+      sP[(2 + i) * NEXT + idx] = ui;
+    }
+    const double p = m.gm1 * (u[D + 1] - 0.5 * ke);
+    sP[0 * NEXT + idx] = p;
+    sP[1 * NEXT + idx] = p * r;
+  }
+  __syncthreads();
+
+  // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
+  for (int e = tid; e < NED; e += NT) {
+    const int a0 = e % G0;
+    const int a1 = (e / G0) % G1;
+    const int a2 = e / (G0 * G1);
+    const int base = a0 + E0 * (a1 + E1 * a2);  // ext index of node i-2
+    EdgeState<D> wl, wr;
+    double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double* col = sP + q * NEXT + base;
+      const double v0 = col[0], v1 = col[STEP], v2 = col[2 * STEP];
+      const double v3 = col[3 * STEP], v4 = col[4 * STEP], v5 = col[5 * STEP];
+      if (m.scheme == AMR_SCHEME_CENTRAL) {
+        lv[q] = central4(v1, v2, v3, v4);
+        rv[q] = lv[q];
+      } else {
+        lv[q] = weno5(v0, v1, v2, v3, v4, m.eps);
+        rv[q] = weno5(v5, v4, v3, v2, v1, m.eps);
+      }
+      lo[q] = v2;
+      hi[q] = v3;
+    }
+    const bool ok = (lv[0] > 0.0) && (lv[1] > 0.0) && (rv[0] > 0.0) && (rv[1] > 0.0);
+    wl.p = ok ? lv[0] : lo[0];
+    wl.T = ok ? lv[1] : lo[1];
+    wr.p = ok ? rv[0] : hi[0];
+    wr.T = ok ? rv[1] : hi[1];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      wl.u[i] = ok ? lv[2 + i] : lo[2 + i];
+      wr.u[i] = ok ? rv[2 + i] : hi[2 + i];
+    }
+    double UL[NV], FL[NV], UR[NV], FR[NV], sl, sr;
+    edge_flux<D, J>(m, wl, UL, FL, sl);
+    edge_flux<D, J>(m, wr, UR, FR, sr);
+    const double S = fmax(sr, sl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v * NED + e] = 0.5 * ((FR[v] + FL[v]) - S * (UR[v] - UL[v]));
+  }
+  __syncthreads();
+
+  // 3. face fluxes G (flux form of Eq. (9)) and their divergence
+  const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
+  constexpr double c24 = 1.0 / 24.0;
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int cell = tid + cc * NT;
+    if (cell >= S::NCELL) break;
+    const int t0 = cell % S::T0;
+    const int t1 = (cell / S::T0) % S::T1;
+    const int t2 = cell / (S::T0 * S::T1);
+    const int tj = J == 0 ? t0 : (J == 1 ? t1 : t2);
+    // edge-array index of edge (t_J - 2 + k) + 1/2 in the edge box
+    int eb;
+    constexpr int ESTEP = J == 0 ? 1 : (J == 1 ? G0 : G0 * G1);
+    if constexpr (J == 0) eb = G0 * (t1 + G1 * t2);
+    else if constexpr (J == 1) eb = t0 + G0 * G1 * t2;
+    else eb = t0 + G0 * t1;
+    eb += tj * ESTEP;
+    const int i = o[J] + tj;
+    int tang = 0;
+    if constexpr (D == 2) tang = (J == 0) ? (o[1] + t1) : (o[0] + t0);
+    if constexpr (D == 3) {
+      if constexpr (J == 0) tang = (o[1] + t1) + n * (o[2] + t2);
+      else if constexpr (J == 1) tang = (o[0] + t0) + n * (o[2] + t2);
+      else tang = (o[0] + t0) + n * (o[1] + t1);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* F = sF + v * NED + eb;
+      const double Fm2 = F[0], Fm1 = F[ESTEP], F0 = F[2 * ESTEP], Fp1 = F[3 * ESTEP];
+      const double Gp = F0 - ((Fm1 - 2.0 * F0) + Fp1) * c24;
+      const double Gm = Fm1 - ((Fm2 - 2.0 * Fm1) + F0) * c24;
+      acc[cc][v] -= (Gp - Gm) * inv_h;
+      if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = Gm;
+      if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = Gp;
+    }
+  }
+  __syncthreads();
+}
+
+template <int D, int TX, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+                                              const double* Un, double* out,
+                                              double* __restrict__ fr,
+                                              const int* __restrict__ tiles, int count,
+                                              const double* __restrict__ dtp) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int CPT = (S::NCELL + NT - 1) / NT;
+  __shared__ double sP[(D + 2) * S::EXTMAX];
+  __shared__ double sF[(D + 2) * S::EDMAX];
+  if ((int)blockIdx.x >= count) return;
+  const int pid = tiles[2 * blockIdx.x];
+  const int tix = tiles[2 * blockIdx.x + 1];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, full = L.full;
+  const int nt0 = n / S::T0, nt1 = n / S::T1;
+  const int o[3] = {(tix % nt0) * S::T0, ((tix / nt0) % nt1) * S::T1, (tix / (nt0 * nt1)) * S::T2};
+  const long long base = patch_base(m, pid, l);
+  const double* Pin = Uin + base;
+  double* frp = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
+  double acc[CPT][NV];
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
+
+  stage_direction<D, TX, TY, TZ, NT, 0>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+  if constexpr (D >= 2)
+    stage_direction<D, TX, TY, TZ, NT, 1>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+  if constexpr (D >= 3)
+    stage_direction<D, TX, TY, TZ, NT, 2>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+
+  const long long vs = var_stride<D>(full);
+  const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
+  constexpr double c23 = 2.0 / 3.0;
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int cell = threadIdx.x + cc * NT;
+    if (cell >= S::NCELL) break;
+    const int t0 = cell % S::T0;
+    const int t1 = (cell / S::T0) % S::T1;
+    const int t2 = cell / (S::T0 * S::T1);
+    const long long off = base + box_off<D>(full, o[0] + t0 + NG, o[1] + t1 + NG, o[2] + t2 + NG);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const long long a = off + v * vs;
+      const double Lv = acc[cc][v];
+      double r;
+      if (mode == kModeRHS) {
+        r = Lv;
+      } else if (mode == kModeStage1) {
+        r = Un[a] + dt * Lv;
+      } else {
+        const double un = Un[a];
+        const double ui = Uin[a];
+        r = un + (mode == kModeStage2 ? 0.25 : c23) * ((ui + dt * Lv) - un);
+      }
+      out[a] = r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// coarse/fine flux correction: list of (pid, face mask); faces are processed
+// in the order x-, x+, y-, y+, z-, z+ so that corner cells see a fixed order
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_reflux(DevMesh m, int mode, double* __restrict__ out,
+                                                const double* __restrict__ fr,
+                                                const int* __restrict__ list, int count,
+                                                const double* __restrict__ dtp, double w) {
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[2 * blockIdx.x];
+  const int mask = list[2 * blockIdx.x + 1];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const LevelC& Fv = m.lv[l + 1];
+  const int n = L.n, nf = Fv.n, Nf = Fv.cells;
+  const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
+  const int nfface = (D == 1) ? 1 : (D == 2 ? nf : nf * nf);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  const double* frc = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
+  double* P = out + patch_base(m, pid, l);
+  const long long vs = var_stride<D>(L.full);
+  const double coef = (mode == kModeRHS) ? L.inv_h : w * dtp[0] * L.inv_h;
+  for (int f = 0; f < 2 * D; ++f) {
+    if (mask & (1 << f)) {
+      const int j = f >> 1, side = f & 1;
+      int tdim[2] = {0, 0}, nt = 0;
+      for (int k = 0; k < D; ++k)
+        if (k != j) tdim[nt++] = k;
+      int F = 2 * (pc[j] * n + (side ? n : 0));
+      int cj;
+      if (side) {
+        F %= Nf;
+        cj = F;
+      } else {
+        if (F == 0) F = Nf;
+        cj = F - 1;
+      }
+      const int fside = side ? 0 : 1;
+      for (int t = threadIdx.x; t < nface; t += blockDim.x) {
+        int tl[2] = {0, 0};
+        if constexpr (D >= 2) tl[0] = t % n;
+        if constexpr (D >= 3) tl[1] = t / n;
+        double sub[4][NV];
+        const int nsub = 1 << (D - 1);
+        bool ok = true;
+        for (int s = 0; s < nsub; ++s) {
+          int q[3] = {0, 0, 0}, fl[2] = {0, 0};
+          q[j] = cj / nf;
+          for (int k = 0; k < D - 1; ++k) {
+            const int gfc = 2 * (pc[tdim[k]] * n + tl[k]) + ((s >> k) & 1);
+            q[tdim[k]] = gfc / nf;
+            fl[k] = gfc - q[tdim[k]] * nf;
+          }
+          const int fpid = map_at<D>(m, l + 1, q);
+          if (fpid < 0) {
+            ok = false;
+            break;
+          }
+          const double* frf = fr + Fv.fr_off + (long long)(fpid - Fv.pid_base) * Fv.fr_stride;
+          const int ft = fl[0] + nf * fl[1];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sub[s][v] = frf[((j * 2 + fside) * NV + v) * nfface + ft];
+        }
+        int c[3] = {0, 0, 0};
+        c[j] = side ? n - 1 : 0;
+        for (int k = 0; k < D - 1; ++k) c[tdim[k]] = tl[k];
+        const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+        const double sgn = side ? 1.0 : -1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double avg;
+          if constexpr (D == 1) avg = sub[0][v];
+          else if constexpr (D == 2) avg = (sub[0][v] + sub[1][v]) * 0.5;
+          else avg = ((sub[0][v] + sub[1][v]) + (sub[2][v] + sub[3][v])) * 0.25;
+          if (!ok) avg = __builtin_nan("");
+          const double gc = frc[((j * 2 + side) * NV + v) * nface + t];
+          P[v * vs + off] += coef * (sgn * (gc - avg));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// restriction of one level: list of child pids; pairwise sums in x-fastest
+// child order, times 2^-D
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
+                                                  const int* __restrict__ list, int count) {
+#pragma clang fp contract(off)
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int cpid = list[blockIdx.x];
+  const int lf = m.level[cpid];
+  const int ppid = m.parent[cpid];
+  const LevelC& F = m.lv[lf];
+  const LevelC& C = m.lv[lf - 1];
+  const int h = F.n / 2;
+  int o[3] = {0, 0, 0};
+  for (int j = 0; j < D; ++j) o[j] = m.coord[3 * cpid + j] * h - m.coord[3 * ppid + j] * C.n;
+  const double* Pc = U + patch_base(m, cpid, lf);
+  double* Pp = U + patch_base(m, ppid, lf - 1);
+  const long long vsf = var_stride<D>(F.full), vsc = var_stride<D>(C.full);
+  int total = h;
+  if constexpr (D >= 2) total *= h;
+  if constexpr (D >= 3) total *= h;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int a = idx % h;
+    const int b = D >= 2 ? (idx / h) % h : 0;
+    const int c = D >= 3 ? idx / (h * h) : 0;
+    const long long dst = box_off<D>(C.full, o[0] + a + NG, o[1] + b + NG, o[2] + c + NG);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double* S = Pc + v * vsf;
+      auto at = [&](int x, int y, int z) {
+        return S[box_off<D>(F.full, 2 * a + x + NG, 2 * b + y + NG, 2 * c + z + NG)];
+      };
+      double r;
+      if constexpr (D == 1) r = (at(0, 0, 0) + at(1, 0, 0)) * 0.5;
+      else if constexpr (D == 2)
+        r = ((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) * 0.25;
+      else
+        r = (((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) +
+             ((at(0, 0, 1) + at(1, 0, 1)) + (at(0, 1, 1) + at(1, 1, 1)))) * 0.125;
+      Pp[v * vsc + dst] = r;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL rate: max over leaf cells of sum_j (|u_j| + c) / h, as IEEE bits of a
+// non-negative double (order-preserving), reduced with a wave shuffle, LDS and
+// one 64-bit atomic max per block
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_max_rate(DevMesh m, const double* __restrict__ U,
+                                                  const int* __restrict__ list, int count,
+                                                  unsigned long long* __restrict__ lam) {
+#pragma clang fp contract(off)
+  constexpr int NV = D + 2;
+  __shared__ unsigned long long red[4];
+  unsigned long long best = 0ull;
+  if ((int)blockIdx.x < count) {
+    const int pid = list[blockIdx.x];
+    const int l = m.level[pid];
+    const LevelC& L = m.lv[l];
+    const int n = L.n;
+    const double* P = U + patch_base(m, pid, l);
+    const long long vs = var_stride<D>(L.full);
+    int total = n;
+    if constexpr (D >= 2) total *= n;
+    if constexpr (D >= 3) total *= n;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int x = idx % n;
+      const int y = D >= 2 ? (idx / n) % n : 0;
+      const int z = D >= 3 ? idx / (n * n) : 0;
+      const long long off = box_off<D>(L.full, x + NG, y + NG, z + NG);
+      double u[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
+      const double rho = u[0];
+      double uj[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) uj[j] = u[1 + j] / rho;
+      double ke = u[1] * uj[0];
+#pragma unroll
+      for (int j = 1; j < D; ++j) ke = ke + u[1 + j] * uj[j];
+      ke = 0.5 * ke;
+      const double p = m.gm1 * (u[D + 1] - ke);
+      const double c = sqrt(m.gamma * p / rho);
+      double s = fabs(uj[0]) + c;
+#pragma unroll
+      for (int j = 1; j < D; ++j) s = s + (fabs(uj[j]) + c);
+      const double r = s / L.h;
+      unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+      if (!(r >= 0.0)) bits = 0x7ff8000000000000ull;  // NaN propagates as the maximum
+      best = bits > best ? bits : best;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off);
+    best = o > best ? o : best;
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = red[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = red[k] > b ? red[k] : b;
+    if (b) atomicMax(lam, b);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
+
+__global__ void k_dt_from_rate(const unsigned long long* __restrict__ lam, double cfl,
+                               double* __restrict__ dt) {
+  dt[0] = cfl / __longlong_as_double((long long)lam[0]);
+}
+
+// ---------------------------------------------------------------------------
+// tagging: per leaf, any cell within tag_buffer of the interior with
+// |phi+ - phi-| > theta (|phi+| + |phi-|) for phi in {rho, p}, any direction
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void rho_p_at(const DevMesh& m, const double* P, long long vs,
+                                         long long off, double& rho, double& p) {
+  double u[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) u[v] = P[v * vs + off];
+  rho = u[0];
+  p = pressure_exact<D>(u, m.gm1);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict__ U,
+                                             const int* __restrict__ list, int count,
+                                             uint8_t* __restrict__ has_tag,
+                                             uint8_t* __restrict__ raw) {
+#pragma clang fp contract(off)
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[blockIdx.x];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, b = m.tag_buffer, w = n + 2 * b;
+  const double* P = U + patch_base(m, pid, l);
+  const long long vs = var_stride<D>(L.full);
+  int total = w;
+  if constexpr (D >= 2) total *= w;
+  if constexpr (D >= 3) total *= w;
+  int any = 0;
+  uint8_t* rp = raw ? raw + L.tag_off + (long long)(pid - L.pid_base) * vs : nullptr;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int c[3] = {idx % w - b, 0, 0};
+    if constexpr (D >= 2) c[1] = (idx / w) % w - b;
+    if constexpr (D >= 3) c[2] = idx / (w * w) - b;
+    bool t = false;
+    for (int j = 0; j < D; ++j) {
+      int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+      cp[j] += 1;
+      cm[j] -= 1;
+      double rp_, pp_, rm_, pm_;
+      rho_p_at<D>(m, P, vs, box_off<D>(L.full, cp[0] + NG, cp[1] + NG, cp[2] + NG), rp_, pp_);
+      rho_p_at<D>(m, P, vs, box_off<D>(L.full, cm[0] + NG, cm[1] + NG, cm[2] + NG), rm_, pm_);
+      t |= fabs(rp_ - rm_) > m.theta * (fabs(rp_) + fabs(rm_));
+      t |= fabs(pp_ - pm_) > m.theta * (fabs(pp_) + fabs(pm_));
+    }
+    any |= t;
+    if (rp) rp[box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG)] = t ? 1 : 0;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) has_tag[pid] = any ? 1 : 0;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_cell_tags(DevMesh m, const uint8_t* __restrict__ raw,
+                                                   const int* __restrict__ list, int count,
+                                                   uint8_t* __restrict__ out) {
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[blockIdx.x];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, b = m.tag_buffer;
+  const long long vs = var_stride<D>(L.full);
+  const uint8_t* rp = raw + L.tag_off + (long long)(pid - L.pid_base) * vs;
+  uint8_t* op = out + L.tag_off + (long long)(pid - L.pid_base) * vs;
+  int total = n;
+  if constexpr (D >= 2) total *= n;
+  if constexpr (D >= 3) total *= n;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int x = idx % n;
+    const int y = D >= 2 ? (idx / n) % n : 0;
+    const int z = D >= 3 ? idx / (n * n) : 0;
+    int t = 0;
+    for (int dz = (D >= 3 ? -b : 0); dz <= (D >= 3 ? b : 0); ++dz)
+      for (int dy = (D >= 2 ? -b : 0); dy <= (D >= 2 ? b : 0); ++dy)
+        for (int dx = -b; dx <= b; ++dx)
+          t |= rp[box_off<D>(L.full, x + dx + NG, y + dy + NG, z + dz + NG)];
+    op[box_off<D>(L.full, x + NG, y + NG, z + NG)] = t ? 1 : 0;
+  }
+}
+
+// refine request: active leaf below the finest level with a tag;
+// coarsen request: patch whose children are all leaves without tags
+__global__ void k_requests(DevMesh m, const uint8_t* __restrict__ has_tag,
+                           const uint8_t* __restrict__ active_leaf, int nslots,
+                           uint8_t* __restrict__ refine, uint8_t* __restrict__ coarsen) {
+  const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid >= nslots) return;
+  const uint8_t al = active_leaf[pid];  // 0 inactive, 1 leaf, 2 non-leaf
+  uint8_t rq = 0, cq = 0;
+  if (al == 1) {
+    rq = (has_tag[pid] && m.level[pid] < m.nlev - 1) ? 1 : 0;
+  } else if (al == 2) {
+    cq = 1;
+    const int nc = m.nchild[pid];
+    for (int k = 0; k < nc; ++k) {
+      const int c = m.child[(long long)pid * m.maxc + k];
+      if (active_leaf[c] != 1 || has_tag[c]) {
+        cq = 0;
+        break;
+      }
+    }
+  }
+  if (refine) refine[pid] = rq;
+  if (coarsen) coarsen[pid] = cq;
+}
+
+// prolongation of the interiors of newly created patches of one level
+template <int D>
+__global__ __launch_bounds__(256) void k_prolong_new(DevMesh m, double* __restrict__ U,
+                                                     const int* __restrict__ list, int count,
+                                                     int* __restrict__ err) {
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[blockIdx.x];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n;
+  double* P = U + patch_base(m, pid, l);
+  const long long vs = var_stride<D>(L.full);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  int total = n;
+  if constexpr (D >= 2) total *= n;
+  if constexpr (D >= 3) total *= n;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int c[3] = {idx % n, 0, 0};
+    if constexpr (D >= 2) c[1] = (idx / n) % n;
+    if constexpr (D >= 3) c[2] = idx / (n * n);
+    int g[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) g[j] = pc[j] * n + c[j];
+    double val[NV];
+    if (!prolong_cell<D>(m, U, l, g, val)) {
+      err[0] = 1;
+      for (int v = 0; v < NV; ++v) val[v] = __builtin_nan("");
+    }
+    const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[v * vs + off] = val[v];
+  }
+}
+
+__global__ void k_scatter_int(int* __restrict__ dst, const int* __restrict__ pairs, int npairs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npairs) dst[pairs[2 * i]] = pairs[2 * i + 1];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restrict__ U,
+                                               const int* __restrict__ list, int count,
+                                               int* __restrict__ bad) {
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[blockIdx.x];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n;
+  const double* P = U + patch_base(m, pid, l);
+  const long long vs = var_stride<D>(L.full);
+  int total = n;
+  if constexpr (D >= 2) total *= n;
+  if constexpr (D >= 3) total *= n;
+  int cnt = 0;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int x = idx % n;
+    const int y = D >= 2 ? (idx / n) % n : 0;
+    const int z = D >= 3 ? idx / (n * n) : 0;
+    double u[NV];
+    const long long off = box_off<D>(L.full, x + NG, y + NG, z + NG);
+    for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
+    const double p = pressure_exact<D>(u, m.gm1);
+    if (!(u[0] > 0.0 && p > 0.0)) ++cnt;
+  }
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(bad, cnt);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+#define AMR_DISPATCH_DIM(dim, KERNEL, GRID, BLOCK, STREAM, ...)                         \
+  do {                                                                                  \
+    if ((dim) == 1) hipLaunchKernelGGL(KERNEL<1>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); \
+    else if ((dim) == 2) hipLaunchKernelGGL(KERNEL<2>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); \
+    else hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__);             \
+  } while (0)
+
+void Kernels::fill(const DevMesh& m, double* U, const int* list, int count, int* err,
+                   hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_fill, dim3(count), dim3(256), s, m, U, list, count, err);
+}
+
+int Kernels::choose_tile(int dim, const int* n, int nlev) {
+  static const int cand[4][2] = {{0, 0}, {16, 8}, {16, 8}, {8, 4}};
+  for (int k = 0; k < 2; ++k) {
+    const int t = cand[dim][k];
+    bool ok = true;
+    for (int l = 0; l < nlev; ++l) ok = ok && (n[l] % t == 0);
+    if (ok) return t;
+  }
+  return 0;
+}
+
+int Kernels::tiles_per_patch(int dim, int tile, int n) {
+  const int r = n / tile;
+  return dim == 1 ? r : (dim == 2 ? r * r : r * r * r);
+}
+
+void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
+                    double* out, double* fr, const int* tiles, int count, const double* dt,
+                    hipStream_t s) {
+  if (count <= 0) return;
+#define AMR_STAGE(D, TX, TY, TZ, NT)                                                      \
+  hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT>), dim3(count), dim3(NT), 0, s, m, mode, Uin, \
+                     Un, out, fr, tiles, count, dt)
+  if (m.dim == 1) {
+    if (m.tile == 16) AMR_STAGE(1, 16, 1, 1, 64);
+    else AMR_STAGE(1, 8, 1, 1, 64);
+  } else if (m.dim == 2) {
+    if (m.tile == 16) AMR_STAGE(2, 16, 16, 1, 320);
+    else AMR_STAGE(2, 8, 8, 1, 128);
+  } else {
+    if (m.tile == 8) AMR_STAGE(3, 8, 8, 8, 704);
+    else AMR_STAGE(3, 4, 4, 4, 128);
+  }
+#undef AMR_STAGE
+}
+
+void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
+                     const int* list, int count, const double* dt, double w, hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_reflux, dim3(count), dim3(256), s, m, mode, out, fr, list, count,
+                   dt, w);
+}
+
+void Kernels::restrict_level(const DevMesh& m, double* U, const int* list, int count,
+                             hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_restrict, dim3(count), dim3(256), s, m, U, list, count);
+}
+
+void Kernels::max_rate(const DevMesh& m, const double* U, const int* list, int count,
+                       unsigned long long* lam, hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_max_rate, dim3(count), dim3(256), s, m, U, list, count, lam);
+}
+
+void Kernels::zero_u64(unsigned long long* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+}
+
+void Kernels::dt_from_rate(const DevMesh& m, const unsigned long long* lam, double* dt,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_from_rate, dim3(1), dim3(1), 0, s, lam, m.cfl, dt);
+}
+
+void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,
+                  uint8_t* has_tag, uint8_t* raw, hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_tag, dim3(count), dim3(256), s, m, U, list, count, has_tag, raw);
+}
+
+void Kernels::cell_tags(const DevMesh& m, const uint8_t* raw, const int* list, int count,
+                        uint8_t* out, hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_cell_tags, dim3(count), dim3(256), s, m, raw, list, count, out);
+}
+
+void Kernels::requests(const DevMesh& m, const uint8_t* has_tag, const uint8_t* active_leaf,
+                       int nslots, uint8_t* refine, uint8_t* coarsen, hipStream_t s) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_requests, dim3((nslots + 255) / 256), dim3(256), 0, s, m, has_tag,
+                     active_leaf, nslots, refine, coarsen);
+}
+
+void Kernels::prolong_new(const DevMesh& m, double* U, const int* list, int count, int* err,
+                          hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_prolong_new, dim3(count), dim3(256), s, m, U, list, count, err);
+}
+
+void Kernels::scatter_int(int* dst, const int* pairs, int npairs, hipStream_t s) {
+  if (npairs <= 0) return;
+  hipLaunchKernelGGL(k_scatter_int, dim3((npairs + 255) / 256), dim3(256), 0, s, dst, pairs,
+                     npairs);
+}
+
+void Kernels::check(const DevMesh& m, const double* U, const int* list, int count, int* bad,
+                    hipStream_t s) {
+  if (count <= 0) return;
+  AMR_DISPATCH_DIM(m.dim, k_check, dim3(count), dim3(256), s, m, U, list, count, bad);
+}
+
+}  // namespace amr

@@ -1,0 +1,296 @@
+"""Parity of the HIP library with the FP64 oracle, call by call (GPU).
+
+Every test builds the oracle's hierarchy from seeded synthetic data, mirrors
+its mesh and state into the library, runs the same operation on both sides
+and compares: ghost fill, prolongation and restriction bitwise; tags and
+meshes exactly; RHS, time step and RK stages to 1e-12 relative L-infinity per
+conserved variable.
+"""
+import math
+import random
+
+import numpy as np
+import pytest
+
+from paper_2508_05020_amd import workloads as W
+from oracle.solver import OracleAMR
+from tests import _harness as H
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["1d", "2d", "2d-wall", "3d", "3d-uneven"]
+
+
+@pytest.fixture(scope="module")
+def amr():
+    import paper_2508_05020_amd.amr as A
+    return A
+
+
+def _pair(name, amr, exec_mode=None):
+    o, gen = H.oracle_for(name)
+    h = amr.Hierarchy(o.cfg, exec_mode=amr.EXEC_BATCHED if exec_mode is None else exec_mode)
+    pid_of, key_of = H.mirror(o, h)
+    return o, h, pid_of, key_of
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fill_ghosts_bitwise(name, amr):
+    o, h, pid_of, _ = _pair(name, amr)
+    d = o.cfg.dim
+    # poison the library's ghost layers, then fill
+    poisoned = {}
+    for k in o.forest.keys():
+        a = o.U[0][k].copy()
+        mask = np.ones(a.shape[1:], bool)
+        mask[(slice(4, a.shape[1] - 4),) * d] = False
+        a[:, mask] = np.nan
+        poisoned[pid_of[k]] = a
+    h.set_state(0, poisoned)
+    h.fill_ghosts(0)
+    assert h.fill_error() == 0
+    o.fill_ghosts(0)
+    got = H.download(h, 0, pid_of)
+    for k in o.forest.keys():
+        assert np.array_equal(got[k], o.U[0][k]), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rhs_parity(name, amr):
+    o, h, pid_of, _ = _pair(name, amr)
+    L = h.rhs(0)
+    o.fill_ghosts(0, o.forest.leaves())
+    ref = o.rhs(0)
+    got = H.tensor_patches(h, L, pid_of)
+    d = o.cfg.dim
+    gint = {k: H.interior(got[k], d) for k in ref}
+    err = H.rel_linf(gint, ref, list(ref), d, region="none")
+    assert err <= H.TOL, err
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_dt_parity(name, amr):
+    o, h, _, _ = _pair(name, amr)
+    dt = float(h.compute_dt(0).item())
+    ref = o.compute_dt(0)
+    assert abs(dt - ref) <= 1e-14 * ref, (dt, ref)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_rk_stages_parity(name, amr):
+    o, h, pid_of, _ = _pair(name, amr)
+    d = o.cfg.dim
+    dt_dev = h.compute_dt(0)
+    dt = o.compute_dt(0)
+    keys = o.forest.keys()
+    for k, buf in ((1, 1), (2, 2), (3, 0)):
+        h.rk_stage(k, dt_dev)
+        o.stage(k, dt)
+        got = H.download(h, buf, pid_of)
+        err = H.rel_linf(got, o.U[buf], keys, d)
+        assert err <= H.TOL, (k, err)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_tag_and_requests_exact(name, amr):
+    o, h, pid_of, key_of = _pair(name, amr)
+    refine, coarsen, cells = h.tag(0, cell_tags=True)
+    o.fill_ghosts(0, o.forest.leaves())
+    has, ocells = o.tag(0)
+    oref, ocoa = o.requests(has)
+    r = refine.cpu().numpy()
+    c = coarsen.cpu().numpy()
+    assert {key_of[p] for p in np.nonzero(r)[0]} == set(oref)
+    assert {key_of[p] for p in np.nonzero(c)[0]} == set(ocoa)
+    flat = cells.cpu().numpy()
+    d = o.cfg.dim
+    for k in o.forest.leaves():
+        n = o.cfg.patch_cells[k[0]] + 8
+        off = h.offset(pid_of[k]) // h.nvar
+        box = flat[off:off + n ** d].reshape((n,) * d)
+        assert np.array_equal(box[(slice(4, n - 4),) * d].astype(bool), ocells[k]), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_regrid_parity(name, amr):
+    o, h, pid_of, key_of = _pair(name, amr)
+    o.fill_ghosts(0, o.forest.leaves())
+    has, _ = o.tag(0)
+    oref, ocoa = o.requests(has)
+    # add coarsening requests on every non-leaf so that the coarsening rule is
+    # exercised where it is allowed
+    ocoa = sorted(set(ocoa) | {k for k in o.forest.keys() if not o.forest.is_leaf(k)})
+    rq = np.zeros(o.cfg.max_patches, np.uint8)
+    cq = np.zeros(o.cfg.max_patches, np.uint8)
+    for k in oref:
+        rq[pid_of[k]] = 1
+    for k in ocoa:
+        cq[pid_of[k]] = 1
+    h.regrid(rq, cq)
+    o.regrid(oref, ocoa)
+    table = h.patch_table()
+    lib_keys = {(t["level"], t["coord"]) for t in table}
+    assert lib_keys == set(o.forest.keys())
+    pid_of = {(t["level"], t["coord"]): t["pid"] for t in table}
+    got = H.download(h, 0, pid_of)
+    d = o.cfg.dim
+    for k in o.forest.keys():
+        assert np.array_equal(H.interior(got[k], d), H.interior(o.U[0][k], d)), k
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d-uneven"])
+def test_lockstep_steps_with_regrid(name, amr):
+    """Several steps with regrids every second step.  Both sides tag their own
+    state; the request sets must agree (no decision within round-off of the
+    threshold is expected), and the oracle's requests drive both regrids."""
+    o, h, pid_of, key_of = _pair(name, amr)
+    d = o.cfg.dim
+    nsteps = 6
+    for s in range(1, nsteps + 1):
+        h.step()
+        o.step()
+        if s % 2 == 0:
+            refine, coarsen, _ = h.tag(0)
+            o.fill_ghosts(0, o.forest.leaves())
+            has, _ = o.tag(0)
+            oref, ocoa = o.requests(has)
+            r = {key_of[p] for p in np.nonzero(refine.cpu().numpy())[0]}
+            c = {key_of[p] for p in np.nonzero(coarsen.cpu().numpy())[0]}
+            assert r == set(oref) and c == set(ocoa), (s, r ^ set(oref), c ^ set(ocoa))
+            rq = np.zeros(o.cfg.max_patches, np.uint8)
+            cq = np.zeros(o.cfg.max_patches, np.uint8)
+            for k in oref:
+                rq[pid_of[k]] = 1
+            for k in ocoa:
+                cq[pid_of[k]] = 1
+            h.regrid(rq, cq)
+            o.regrid(oref, ocoa)
+            pid_of = {(t["level"], t["coord"]): t["pid"] for t in h.patch_table()}
+            key_of = {v: k for k, v in pid_of.items()}
+            assert set(pid_of) == set(o.forest.keys())
+    got = H.download(h, 0, pid_of)
+    err = H.rel_linf(got, o.U[0], o.forest.keys(), d)
+    assert err <= H.TOL, err
+
+
+@pytest.mark.parametrize("name", ["1d", "2d", "3d"])
+def test_batched_equals_per_patch_bitwise(name, amr):
+    o, h1, pid1, _ = _pair(name, amr, exec_mode=amr.EXEC_BATCHED)
+    o2, h2, pid2, _ = _pair(name, amr, exec_mode=amr.EXEC_PER_PATCH)
+    for _ in range(2):
+        h1.step()
+        h2.step()
+    h1.adapt()
+    h2.adapt()
+    h1.step()
+    h2.step()
+    t1 = {(t["level"], t["coord"]): t["pid"] for t in h1.patch_table()}
+    t2 = {(t["level"], t["coord"]): t["pid"] for t in h2.patch_table()}
+    assert set(t1) == set(t2)
+    a = H.download(h1, 0, t1)
+    b = H.download(h2, 0, t2)
+    d = o.cfg.dim
+    for k in t1:
+        assert np.array_equal(H.interior(a[k], d), H.interior(b[k], d)), k
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_uniform_state_bitwise_gpu(d, amr):
+    base = {1: 64, 2: 64, 3: 32}[d]
+    cfg = W.AMRConfig(name="u", dim=d, base_cells=base, patch_cells=[8, 8, 8],
+                      periodic=[True] * (d - 1) + [False], max_patches=8192)
+    h = amr.Hierarchy(cfg)
+    gen = W.uniform_state(d, 900 + d)
+    amr.init_from_ic(h, gen)
+    ref = amr.patch_primitives(cfg, 0, (0,) * d, gen)
+    rnd = random.Random(d)
+    U0 = None
+    for it in range(4):
+        table = h.patch_table()
+        leaves = [t for t in table if t["nchildren"] == 0 and t["level"] < cfg.max_levels - 1]
+        rq = np.zeros(cfg.max_patches, np.uint8)
+        for t in rnd.sample(leaves, max(1, len(leaves) // 4)):
+            rq[t["pid"]] = 1
+        cq = np.zeros_like(rq)
+        if it == 2:
+            for t in table:
+                if t["nchildren"]:
+                    cq[t["pid"]] = rnd.random() < 0.5
+        h.regrid(rq, cq)
+        h.step()
+    table = h.patch_table()
+    assert max(t["level"] for t in table) >= 1
+    levels = {t["pid"]: t["level"] for t in table}
+    got = h.get_state(0, list(levels), levels)
+    first = None
+    for p, a in got.items():
+        inner = H.interior(a, d).reshape(d + 2, -1)
+        if first is None:
+            first = inner[:, 0].copy()
+        assert np.all(inner == first[:, None]), p
+
+
+def test_conservation_gpu(amr):
+    o, h, pid_of, _ = _pair("2d", amr)
+    d = 2
+
+    def totals():
+        table = h.patch_table()
+        leaves = {t["pid"]: t["level"] for t in table if t["nchildren"] == 0}
+        got = h.get_state(0, list(leaves), leaves)
+        out = []
+        for v in range(4):
+            vals = []
+            for p, a in got.items():
+                vals.extend((H.interior(a, d)[v] * o.cfg.h(leaves[p]) ** d).ravel().tolist())
+            out.append(math.fsum(vals))
+        return np.array(out), got
+
+    t0, got = totals()
+    scale = max(abs(t0[-1]), 1.0)
+    for s in range(8):
+        h.step()
+        if s % 2 == 1:
+            h.adapt()
+    t1, _ = totals()
+    assert np.max(np.abs(t1 - t0)) / scale <= 1e-13 * 8
+
+
+def test_full_size_c2_one_step(amr):
+    """The benchmark workload (C2: 256^2 base, 3 levels) in the benchmark's
+    launch configuration: every leaf cell after one step."""
+    cfg = W.config("c2")
+    o = OracleAMR(cfg)
+    o.init_from_ic(W.initial_data(cfg, 2001))
+    h = amr.Hierarchy(cfg)
+    pid_of, _ = H.mirror(o, h, bufs=(0,))
+    h.step()
+    o.step()
+    got = H.download(h, 0, pid_of)
+    err = H.rel_linf(got, o.U[0], o.forest.keys(), 2)
+    assert err <= H.TOL, err
+
+
+def test_capacity_error_is_transactional(amr):
+    cfg = W.AMRConfig(name="cap", dim=2, base_cells=64, patch_cells=[16, 16, 16],
+                      periodic=[True, True], max_patches=16 + 8 + 8)
+    h = amr.Hierarchy(cfg)
+    amr.init_from_ic(h, W.uniform_state(2, 5))
+    before = h.patch_table()
+    rq = np.zeros(cfg.max_patches, np.uint8)
+    rq[:16] = 1  # every root: 64 children do not fit in 8 slots
+    with pytest.raises(amr.AMRError) as e:
+        h.regrid(rq, np.zeros_like(rq))
+    assert e.value.status == -2
+    assert h.patch_table() == before
+    h.step()
+    assert h.check() == 0
+
+
+def test_nonphysical_detected(amr):
+    o, h, pid_of, _ = _pair("2d", amr)
+    k = o.forest.leaves()[3]
+    a = o.U[0][k].copy()
+    a[3, 6, 7] = -1.0  # negative total energy -> negative pressure
+    h.set_state(0, {pid_of[k]: a})
+    assert h.check() >= 1
