@@ -64,6 +64,24 @@ def cpu_baseline(cfg, seed: int):
                       f"{dt:.1f} s"}
 
 
+def copy_calibration() -> int:
+    """10 copies of 1 GiB between two device buffers: a kernel whose HBM
+    traffic is known (1 GiB read + 1 GiB written per launch)."""
+    import torch
+    n = 1 << 27  # float64 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes_per_launch": 2 * 8 * n, "launches": 10,
+                      "GBps": 10 * 2 * 8 * n / dt / 1e9}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +91,11 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=2001)
     ap.add_argument("--exec", dest="exec_mode", default="batched", choices=["batched", "per_patch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (scales HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in the design notes, not built.",

@@ -183,9 +183,9 @@ amr_status amr_check(amr_hierarchy* h, int* nonphysical_count);
 /* Pids created by the most recent regrid, in creation order (no device work). */
 amr_status amr_last_created(const amr_hierarchy* h, int* pids, int cap, int* n);
 
-/* Reads and returns the sticky ghost-fill/prolongation error flag: 1 when a
- * fill found no same-level or coarser source for a ghost cell (invalid mesh)
- * since the last regrid (sync). */
+/* Reads and clears the sticky ghost-fill/prolongation error flag: 1 when a
+ * fill or the prolongation of a new patch found no same-level or coarser
+ * source (an invalid mesh) since the flag was last read (sync). */
 amr_status amr_fill_error(amr_hierarchy* h, int* flag);
 
 /* Host-only replay of mesh adaptation, for checking the refinement and
@@ -209,9 +209,66 @@ amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells);
 amr_status amr_profile(amr_hierarchy* h, int enable);
 amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, int64_t* cells);
 
+/* The plain tagger as judge (sync): *uncovered = number of leaves below the
+ * finest level that the gradient tagger would refine now on U^n (0 = the
+ * current mesh covers every tag). */
+amr_status amr_judge(amr_hierarchy* h, int* uncovered);
+
 /* Execution mode switch (AMR_EXEC_PER_PATCH launches one kernel per patch per
  * phase; AMR_EXEC_BATCHED launches each phase once over all patches). */
 amr_status amr_set_exec_mode(amr_hierarchy* h, int mode);
+
+/* ------------------------------------------------------------------------
+ * Learned refinement predictor (2D; not part of the paper).  A per-patch
+ * convolutional network forecasts which cells the gradient tagger will tag
+ * within the next steps, so that regridding can run less often; the plain
+ * tagger remains the judge.  Input: normalised (rho, u, v, p) of an n x n
+ * patch plus 3 halo cells, BF16, pixel-major with 4 channels innermost
+ * ([npatch][(n+6)^2][4]).  Network: three valid 3x3 convolutions 4 -> 16 ->
+ * 16 -> 1, bias, ReLU after the first two; BF16 weights and activations,
+ * FP32 accumulation (MFMA); output logits [npatch][n^2] (FP32).
+ * Parameters (FP32 master, 3057 floats): W1 [16][4][3][3], b1 [16],
+ * W2 [16][16][3][3], b2 [16], W3 [16][3][3], b3.  Training: weighted binary
+ * cross-entropy with logits averaged over cells, gradients reduced over
+ * patches in a fixed order, Adam (beta 0.9 / 0.999, eps 1e-8) on the master
+ * weights followed by a round-to-nearest-even BF16 copy.
+ * ---------------------------------------------------------------------- */
+typedef struct amr_cnn amr_cnn;
+typedef struct {
+  int patch_cells;   /* n: leaves whose edge is n are predicted */
+  float mean[4];     /* normalisation of (rho, u, v, p) */
+  float std[4];
+  float pos_weight;  /* weight of the positive class in the loss */
+  int max_batch;     /* patches per forward/training call (1..4096) */
+} amr_cnn_config;
+
+/* Buffers of the predictor come from the hierarchy's allocator (sync). */
+amr_status amr_cnn_create(amr_hierarchy* h, const amr_cnn_config* cfg, amr_cnn** out);
+amr_status amr_cnn_destroy(amr_cnn* c);
+amr_status amr_cnn_num_params(const amr_cnn* c, int* n);
+/* FP32 master weights from / to the host (sync); setting resets Adam. */
+amr_status amr_cnn_set_weights(amr_cnn* c, const float* host_fp32, int n);
+amr_status amr_cnn_get_weights(amr_cnn* c, float* host_fp32, int n);
+/* Input tiles of the given leaf pids of buffer `buf` (ghosts filled first)
+ * into x_dev (sync). */
+amr_status amr_cnn_gather(amr_cnn* c, int buf, const int* pids_host, int npatch, uint16_t* x_dev);
+/* Logits of npatch <= max_batch input tiles (async). */
+amr_status amr_cnn_forward(amr_cnn* c, const uint16_t* x_dev, int npatch, float* logits_dev);
+/* Forward, loss (-> *loss_dev), backward; if lr > 0 one Adam step (async).
+ * labels_dev: [npatch][n^2] bytes (0/1); grads_dev (nullable) receives the
+ * summed parameter gradient. */
+amr_status amr_cnn_train_step(amr_cnn* c, const uint16_t* x_dev, const uint8_t* labels_dev,
+                              int npatch, float lr, float* loss_dev, float* grads_dev);
+/* Predicted requests on buffer `buf` (sync): a leaf of edge n is flagged when
+ * any cell has probability > tau; refine_req = flagged leaves below the
+ * finest level, coarsen_req = patches whose children are all unflagged
+ * leaves (both per pid, max_patches bytes, device). */
+amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_dev,
+                           uint8_t* coarsen_req_dev);
+/* D = A B for 16x16 BF16 matrices on one wave (checks the MFMA lane layout
+ * the predictor kernels assume; async). */
+amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const uint16_t* b_dev,
+                                 float* d_dev);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,11 @@ class PatchInfo(C.Structure):
                 ("nbr", C.c_int32 * 26)]
 
 
+class CnnConfig(C.Structure):
+    _fields_ = [("patch_cells", C.c_int), ("mean", C.c_float * 4), ("std", C.c_float * 4),
+                ("pos_weight", C.c_float), ("max_batch", C.c_int)]
+
+
 class Allocator(C.Structure):
     _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
                 ("free", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)),
@@ -92,6 +97,17 @@ _sigs = {
     "amr_leaf_cells": [_H, _P(C.c_int64)],
     "amr_profile": [_H, C.c_int],
     "amr_profile_read": [_H, _P(C.c_double), _P(C.c_int), _P(C.c_int64)],
+    "amr_cnn_create": [_H, C.c_void_p, _P(_H)],
+    "amr_cnn_destroy": [_H],
+    "amr_cnn_num_params": [_H, _P(C.c_int)],
+    "amr_cnn_set_weights": [_H, C.c_void_p, C.c_int],
+    "amr_cnn_get_weights": [_H, C.c_void_p, C.c_int],
+    "amr_cnn_gather": [_H, C.c_int, _P(C.c_int), C.c_int, C.c_void_p],
+    "amr_cnn_forward": [_H, C.c_void_p, C.c_int, C.c_void_p],
+    "amr_cnn_train_step": [_H, C.c_void_p, C.c_void_p, C.c_int, C.c_float, C.c_void_p, C.c_void_p],
+    "amr_cnn_predict": [_H, C.c_int, C.c_float, C.c_void_p, C.c_void_p],
+    "amr_cnn_mfma_selftest": [_H, C.c_void_p, C.c_void_p, C.c_void_p],
+    "amr_judge": [_H, _P(C.c_int)],
     "amr_forest_replay": [_P(Config), _P(C.c_int32), C.c_int, _P(PatchInfo), C.c_int, _P(C.c_int)],
 }
 for _name, _args in _sigs.items():
@@ -364,8 +380,87 @@ class Hierarchy:
         self._ok(_lib.amr_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells)))
         return ms.value, n.value, cells.value
 
+    def judge(self) -> int:
+        n = C.c_int()
+        self._ok(_lib.amr_judge(self.h, C.byref(n)))
+        return n.value
+
     def set_exec_mode(self, mode: int):
         self._ok(_lib.amr_set_exec_mode(self.h, mode))
+
+
+class Predictor:
+    """The learned refinement predictor of a 2D hierarchy (device weights)."""
+
+    def __init__(self, hier: "Hierarchy", patch_cells: int, mean, std, pos_weight: float = 1.0,
+                 max_batch: int = 256):
+        self.hier = hier
+        self.torch = hier.torch
+        self.n = patch_cells
+        self.max_batch = max_batch
+        c = CnnConfig()
+        c.patch_cells = patch_cells
+        for k in range(4):
+            c.mean[k] = float(mean[k])
+            c.std[k] = float(std[k])
+        c.pos_weight = pos_weight
+        c.max_batch = max_batch
+        self._c = c
+        self.h = _H()
+        hier._ok(_lib.amr_cnn_create(hier.h, C.byref(c), C.byref(self.h)))
+        n = C.c_int()
+        hier._ok(_lib.amr_cnn_num_params(self.h, C.byref(n)))
+        self.nparams = n.value
+        self._loss = self.torch.zeros(1, dtype=self.torch.float32, device=hier.device)
+
+    def close(self):
+        if self.h:
+            _lib.amr_cnn_destroy(self.h)
+            self.h = _H()
+
+    def set_weights(self, w: np.ndarray):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self.hier._ok(_lib.amr_cnn_set_weights(self.h, w.ctypes.data_as(C.c_void_p), w.size))
+
+    def get_weights(self) -> np.ndarray:
+        w = np.empty(self.nparams, np.float32)
+        self.hier._ok(_lib.amr_cnn_get_weights(self.h, w.ctypes.data_as(C.c_void_p), w.size))
+        return w
+
+    def tile_shape(self):
+        return ((self.n + 6) ** 2, 4)
+
+    def gather(self, buf: int, pids):
+        t = self.torch
+        x = t.empty((len(pids),) + self.tile_shape(), dtype=t.int16, device=self.hier.device)
+        arr = (C.c_int * max(1, len(pids)))(*pids)
+        self.hier._ok(_lib.amr_cnn_gather(self.h, buf, arr, len(pids), Hierarchy._ptr(x)))
+        return x
+
+    def forward(self, x):
+        t = self.torch
+        z = t.empty((x.shape[0], self.n * self.n), dtype=t.float32, device=self.hier.device)
+        self.hier._ok(_lib.amr_cnn_forward(self.h, Hierarchy._ptr(x), x.shape[0], Hierarchy._ptr(z)))
+        return z
+
+    def train_step(self, x, labels, lr: float, grads=None):
+        self.hier._ok(_lib.amr_cnn_train_step(self.h, Hierarchy._ptr(x), Hierarchy._ptr(labels),
+                                              x.shape[0], C.c_float(lr), Hierarchy._ptr(self._loss),
+                                              Hierarchy._ptr(grads)))
+        return self._loss
+
+    def predict(self, buf: int, tau: float):
+        t = self.torch
+        mp = self.hier.cfg.max_patches
+        r = t.zeros(mp, dtype=t.uint8, device=self.hier.device)
+        c = t.zeros(mp, dtype=t.uint8, device=self.hier.device)
+        self.hier._ok(_lib.amr_cnn_predict(self.h, buf, C.c_float(tau), Hierarchy._ptr(r),
+                                           Hierarchy._ptr(c)))
+        return r, c
+
+
+def mfma_selftest(hier: "Hierarchy", a, b, d):
+    hier._ok(_lib.amr_cnn_mfma_selftest(hier.h, Hierarchy._ptr(a), Hierarchy._ptr(b), Hierarchy._ptr(d)))
 
 
 def forest_replay(cfg, rounds, coarsen_rule: int = COARSEN_TEXT):

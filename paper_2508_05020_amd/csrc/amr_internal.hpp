@@ -82,6 +82,7 @@ struct Kernels {
   static void prolong_new(const DevMesh& m, double* U, const int* list, int count, int* err,
                           hipStream_t s);
   static void scatter_int(int* dst, const int* pairs, int npairs, hipStream_t s);
+  static void count_nonzero(const uint8_t* a, int n, int* out, hipStream_t s);
   static void check(const DevMesh& m, const double* U, const int* list, int count,
                     int* bad, hipStream_t s);
   // Largest supported tile edge dividing every level's patch edge (0: none).

@@ -12,6 +12,7 @@
 
 #include "amr_internal.hpp"
 #include "forest.hpp"
+#include "cnn_internal.hpp"
 
 namespace {
 
@@ -71,6 +72,10 @@ struct amr_hierarchy {
   long long lists_cap = 0;
   int* d_pairs = nullptr;
   long long pairs_cap = 0;
+  // pinned host staging for table/list uploads (reused; every regrid first
+  // drains the stream, so earlier copies from it have completed)
+  char* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
 
   // host mirrors of the work lists
   std::vector<int> lists;
@@ -115,6 +120,8 @@ struct amr_hierarchy {
     return p;
   }
   void release_all() {
+    if (h_stage) (void)hipHostFree(h_stage);
+    h_stage = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     for (void* p : owned) {
@@ -316,8 +323,17 @@ void sync_tables(amr_hierarchy* h, bool full) {
   }
   ns[f.nlev] = begin_list();
   if ((long long)L.size() > h->lists_cap) throw StateError("work-list buffer too small");
+  const long long np = (long long)pairs.size() / 2;
+  if (np > h->pairs_cap) throw StateError("table update buffer too small");
+  char* st = h->h_stage;
+  int* sl = (int*)st;
+  int* sp = sl + h->lists_cap;
+  uint8_t* sa = (uint8_t*)(sp + 2 * h->pairs_cap);
+  std::copy(L.begin(), L.end(), sl);
+  std::copy(pairs.begin(), pairs.end(), sp);
+  std::copy(h->h_active_leaf.begin(), h->h_active_leaf.end(), sa);
   if (!L.empty())
-    HIP_OK(hipMemcpyAsync(h->d_lists, L.data(), L.size() * sizeof(int), hipMemcpyHostToDevice,
+    HIP_OK(hipMemcpyAsync(h->d_lists, sl, L.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
   h->all = {h->d_lists + a0, a1 - a0};
   h->leaves = {h->d_lists + a1, t0 - a1};
@@ -327,17 +343,13 @@ void sync_tables(amr_hierarchy* h, bool full) {
     h->restr[l] = {h->d_lists + rs[l], rs[l + 1] - rs[l]};
     h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
   }
-  HIP_OK(hipMemcpyAsync(h->d_active_leaf, h->h_active_leaf.data(), mp, hipMemcpyHostToDevice,
-                        h->stream));
-  if (!pairs.empty()) {
-    const long long np = (long long)pairs.size() / 2;
-    if (np > h->pairs_cap) throw StateError("table update buffer too small");
-    HIP_OK(hipMemcpyAsync(h->d_pairs, pairs.data(), pairs.size() * sizeof(int),
-                          hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipMemcpyAsync(h->d_active_leaf, sa, mp, hipMemcpyHostToDevice, h->stream));
+  if (np > 0) {
+    HIP_OK(hipMemcpyAsync(h->d_pairs, sp, pairs.size() * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
     Kernels::scatter_int(h->d_tab, h->d_pairs, (int)np, h->stream);
     h->check_launch();
   }
-  h->sync();  // host vectors above are reused by the next call
 }
 
 // Per-patch mode launches one kernel per list entry (the unfused baseline).
@@ -433,15 +445,12 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
   }
   h->last_created = created;
   sync_tables(h, false);
-  clear_flags(h);
+  // a missing prolongation source (impossible on a valid mesh) raises the
+  // sticky error flag read by amr_fill_error; no synchronisation here
   for (int l = 1; l < h->forest.nlev; ++l)
     over_list(h, h->fresh[l], 1, [&](const int* p, int c) {
       Kernels::prolong_new(h->dm, h->U[0], p, c, h->d_flags, h->stream);
     });
-  if (read_flag(h, 0)) {
-    h->err = "prolongation source missing for a new patch";
-    return AMR_E_MESH;
-  }
   if (ncreated) *ncreated = (int)created.size();
   if (ndeleted) *ndeleted = (int)deleted.size();
   return AMR_OK;
@@ -531,6 +540,9 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
     h->d_pairs = (int*)h->dev_alloc(h->pairs_cap * 2 * sizeof(int));
+    h->h_stage_bytes = (size_t)h->lists_cap * sizeof(int) + (size_t)h->pairs_cap * 2 * sizeof(int) +
+                       (size_t)mp + 256;
+    HIP_OK(hipHostMalloc((void**)&h->h_stage, h->h_stage_bytes, hipHostMallocDefault));
     HIP_OK(hipMemsetAsync(h->d_has_tag, 0, mp, h->stream));
     HIP_OK(hipMemsetAsync(h->fr, 0, h->fr_doubles * sizeof(double), h->stream));
     amr::DevMesh& m = h->dm;
@@ -792,7 +804,7 @@ amr_status amr_adapt(amr_hierarchy* h, int* ncreated, int* ndeleted) {
 amr_status amr_check(amr_hierarchy* h, int* nonphysical_count) {
   if (!h) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
-    clear_flags(h);
+    HIP_OK(hipMemsetAsync(h->d_flags + 1, 0, sizeof(int), h->stream));
     over_list(h, h->leaves, 1, [&](const int* p, int c) {
       Kernels::check(h->dm, h->U[0], p, c, h->d_flags + 1, h->stream);
     });
@@ -802,6 +814,18 @@ amr_status amr_check(amr_hierarchy* h, int* nonphysical_count) {
       h->err = "non-physical leaf cells (rho <= 0, p <= 0 or NaN)";
       return AMR_E_NONPHYSICAL;
     }
+    return AMR_OK;
+  });
+}
+
+amr_status amr_judge(amr_hierarchy* h, int* uncovered) {
+  if (!h || !uncovered) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_tag(h, 0, h->d_refine, nullptr, nullptr);
+    HIP_OK(hipMemsetAsync(h->d_flags + 2, 0, sizeof(int), h->stream));
+    Kernels::count_nonzero(h->d_refine, h->forest.max_patches, h->d_flags + 2, h->stream);
+    h->check_launch();
+    *uncovered = read_flag(h, 2);
     return AMR_OK;
   });
 }
@@ -823,6 +847,7 @@ amr_status amr_fill_error(amr_hierarchy* h, int* flag) {
   if (!h || !flag) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
     *flag = read_flag(h, 0);
+    HIP_OK(hipMemsetAsync(h->d_flags, 0, sizeof(int), h->stream));
     return AMR_OK;
   });
 }
@@ -910,6 +935,229 @@ amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, i
     *total_ms = ms;
     *launches = (int)h->ev_cells.size();
     *cells = c;
+    return AMR_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned refinement predictor
+// ---------------------------------------------------------------------------
+struct amr_cnn {
+  amr_hierarchy* h = nullptr;
+  amr_cnn_config cfg{};
+  amr::CnnNorm norm{};
+  int n = 0, max_batch = 0, t = 0;
+  std::vector<void*> owned;
+  float* params = nullptr;   // FP32 master
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grads = nullptr;
+  unsigned short* wb = nullptr;  // BF16 copy
+  unsigned short* X = nullptr;   // max_batch input tiles
+  unsigned short* A1 = nullptr;
+  unsigned short* A2 = nullptr;
+  float* Z = nullptr;
+  float* G = nullptr;
+  float* partials = nullptr;
+  float* loss_part = nullptr;
+  int loss_blocks = 0;
+  int* d_pids = nullptr;
+  uint8_t* d_pred = nullptr;
+  void* alloc(size_t bytes) {
+    void* p = h->dev_alloc(bytes);
+    owned.push_back(p);
+    return p;
+  }
+};
+
+extern "C" {
+
+amr_status amr_cnn_create(amr_hierarchy* h, const amr_cnn_config* cfg, amr_cnn** out) {
+  if (!h || !cfg || !out) return AMR_E_ARG;
+  *out = nullptr;
+  return guarded(h, [&]() -> amr_status {
+    if (h->cfg.dim != 2) throw ArgError("the predictor is implemented for 2D hierarchies");
+    if (cfg->patch_cells < 8 || cfg->patch_cells > 32 || cfg->patch_cells % 2)
+      throw ArgError("predictor patch edge must be even, 8..32");
+    if (cfg->max_batch < 1 || cfg->max_batch > 4096) throw ArgError("max_batch must be 1..4096");
+    amr_cnn* c = new amr_cnn();
+    c->h = h;
+    c->cfg = *cfg;
+    c->n = cfg->patch_cells;
+    c->max_batch = cfg->max_batch;
+    for (int k = 0; k < 4; ++k) {
+      if (!(cfg->std[k] > 0.f)) {
+        delete c;
+        throw ArgError("normalisation std must be positive");
+      }
+      c->norm.mean[k] = cfg->mean[k];
+      c->norm.istd[k] = 1.0f / cfg->std[k];
+    }
+    const int n = c->n, N = c->max_batch;
+    const long long P0 = (n + 6) * (n + 6), P1 = (n + 4) * (n + 4), P2 = (n + 2) * (n + 2);
+    c->params = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
+    c->m = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
+    c->v = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
+    c->grads = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
+    c->wb = (unsigned short*)c->alloc(amr::CNN_NPARAM * sizeof(unsigned short));
+    c->X = (unsigned short*)c->alloc(N * P0 * 4 * sizeof(unsigned short));
+    c->A1 = (unsigned short*)c->alloc(N * P1 * 16 * sizeof(unsigned short));
+    c->A2 = (unsigned short*)c->alloc(N * P2 * 16 * sizeof(unsigned short));
+    c->Z = (float*)c->alloc((long long)N * n * n * sizeof(float));
+    c->G = (float*)c->alloc((long long)N * n * n * sizeof(float));
+    c->partials = (float*)c->alloc((long long)N * amr::CNN_NPARAM * sizeof(float));
+    c->loss_blocks = 256;
+    c->loss_part = (float*)c->alloc((c->loss_blocks + 1) * sizeof(float));
+    c->d_pids = (int*)c->alloc((size_t)h->forest.max_patches * sizeof(int));
+    c->d_pred = (uint8_t*)c->alloc(h->forest.max_patches);
+    HIP_OK(hipMemsetAsync(c->params, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
+    HIP_OK(hipMemsetAsync(c->m, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
+    HIP_OK(hipMemsetAsync(c->v, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
+    HIP_OK(hipMemsetAsync(c->wb, 0, amr::CNN_NPARAM * sizeof(unsigned short), h->stream));
+    h->sync();
+    *out = c;
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_destroy(amr_cnn* c) {
+  if (!c) return AMR_E_ARG;
+  amr_hierarchy* h = c->h;
+  (void)hipStreamSynchronize(h->stream);
+  for (void* p : c->owned) {
+    auto it = std::find(h->owned.begin(), h->owned.end(), p);
+    if (it != h->owned.end()) h->owned.erase(it);
+    if (h->has_alloc) h->alloc.free(p, h->alloc.ctx);
+    else (void)hipFree(p);
+  }
+  delete c;
+  return AMR_OK;
+}
+
+amr_status amr_cnn_num_params(const amr_cnn* c, int* n) {
+  if (!c || !n) return AMR_E_ARG;
+  *n = amr::CNN_NPARAM;
+  return AMR_OK;
+}
+
+amr_status amr_cnn_set_weights(amr_cnn* c, const float* host, int n) {
+  if (!c || !host || n != amr::CNN_NPARAM) return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    HIP_OK(hipMemcpyAsync(c->params, host, n * sizeof(float), hipMemcpyHostToDevice, c->h->stream));
+    HIP_OK(hipMemsetAsync(c->m, 0, n * sizeof(float), c->h->stream));
+    HIP_OK(hipMemsetAsync(c->v, 0, n * sizeof(float), c->h->stream));
+    amr::Cnn::to_bf16(c->params, c->wb, c->h->stream);
+    c->h->check_launch();
+    c->t = 0;
+    c->h->sync();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_get_weights(amr_cnn* c, float* host, int n) {
+  if (!c || !host || n != amr::CNN_NPARAM) return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    HIP_OK(hipMemcpyAsync(host, c->params, n * sizeof(float), hipMemcpyDeviceToHost, c->h->stream));
+    c->h->sync();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_gather(amr_cnn* c, int buf, const int* pids_host, int npatch, uint16_t* x_dev) {
+  if (!c || !buf_ok(buf) || npatch < 0 || (npatch > 0 && (!pids_host || !x_dev))) return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    amr_hierarchy* h = c->h;
+    for (int i = 0; i < npatch; ++i) {
+      const int p = pids_host[i];
+      if (p < 0 || p >= h->forest.max_patches || !h->forest.active[p] ||
+          h->forest.n[h->forest.level[p]] != c->n)
+        throw ArgError("gather: pid inactive or of another patch size");
+    }
+    if (npatch > h->forest.max_patches) throw ArgError("too many pids");
+    do_fill(h, buf, h->leaves);
+    HIP_OK(hipMemcpyAsync(c->d_pids, pids_host, npatch * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
+    amr::Cnn::gather(h->dm, h->U[buf], c->d_pids, npatch, c->n, c->norm, (unsigned short*)x_dev,
+                     h->stream);
+    h->check_launch();
+    h->sync();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_forward(amr_cnn* c, const uint16_t* x_dev, int npatch, float* logits_dev) {
+  if (!c || !x_dev || !logits_dev || npatch < 0 || npatch > c->max_batch) return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    amr::Cnn::forward(npatch, c->n, (const unsigned short*)x_dev, c->wb, c->params, nullptr,
+                      nullptr, logits_dev, c->h->stream);
+    c->h->check_launch();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_train_step(amr_cnn* c, const uint16_t* x_dev, const uint8_t* labels_dev,
+                              int npatch, float lr, float* loss_dev, float* grads_dev) {
+  if (!c || !x_dev || !labels_dev || !loss_dev || npatch < 1 || npatch > c->max_batch)
+    return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    hipStream_t s = c->h->stream;
+    const unsigned short* X = (const unsigned short*)x_dev;
+    amr::Cnn::forward(npatch, c->n, X, c->wb, c->params, c->A1, c->A2, c->Z, s);
+    const long long total = (long long)npatch * c->n * c->n;
+    amr::Cnn::loss(total, c->Z, labels_dev, c->cfg.pos_weight, c->G, c->loss_part,
+                   c->loss_blocks, loss_dev, s);
+    amr::Cnn::backward(npatch, c->n, X, c->A1, c->A2, c->G, c->wb, c->partials, c->grads, s);
+    if (grads_dev)
+      HIP_OK(hipMemcpyAsync(grads_dev, c->grads, amr::CNN_NPARAM * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
+    if (lr > 0.f) {
+      c->t += 1;
+      amr::Cnn::adam(c->params, c->grads, c->m, c->v, lr, c->t, c->wb, s);
+    }
+    c->h->check_launch();
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_dev,
+                           uint8_t* coarsen_req_dev) {
+  if (!c || !buf_ok(buf) || !(tau > 0.f && tau < 1.f)) return AMR_E_ARG;
+  return guarded(c->h, [&]() -> amr_status {
+    amr_hierarchy* h = c->h;
+    hipStream_t s = h->stream;
+    std::vector<int> pids;
+    for (int pid = 0; pid < h->forest.max_patches; ++pid)
+      if (h->forest.active[pid] && h->forest.is_leaf(pid) && h->forest.n[h->forest.level[pid]] == c->n)
+        pids.push_back(pid);
+    do_fill(h, buf, h->leaves);
+    HIP_OK(hipMemsetAsync(c->d_pred, 0, h->forest.max_patches, s));
+    if (!pids.empty())
+      HIP_OK(hipMemcpyAsync(c->d_pids, pids.data(), pids.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    const float zt = std::log(tau / (1.0f - tau));
+    for (size_t b0 = 0; b0 < pids.size(); b0 += (size_t)c->max_batch) {
+      const int cnt = (int)std::min<size_t>(c->max_batch, pids.size() - b0);
+      amr::Cnn::gather(h->dm, h->U[buf], c->d_pids + b0, cnt, c->n, c->norm, c->X, s);
+      amr::Cnn::forward(cnt, c->n, c->X, c->wb, c->params, nullptr, nullptr, c->Z, s);
+      amr::Cnn::requests(cnt, c->n, c->Z, c->d_pids + b0, zt, c->d_pred, s);
+    }
+    Kernels::requests(h->dm, c->d_pred, h->d_active_leaf, h->forest.max_patches, refine_req_dev,
+                      coarsen_req_dev, s);
+    h->check_launch();
+    h->sync();  // pids (host vector) copied
+    return AMR_OK;
+  });
+}
+
+amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const uint16_t* b_dev,
+                                 float* d_dev) {
+  if (!h || !a_dev || !b_dev || !d_dev) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    amr::Cnn::mfma_selftest((const unsigned short*)a_dev, (const unsigned short*)b_dev, d_dev,
+                            h->stream);
+    h->check_launch();
     return AMR_OK;
   });
 }

@@ -14,6 +14,7 @@
 // values.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -198,6 +199,16 @@ __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
 // nonlinear weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
 // t_k = (eps + beta_k)^2, are evaluated as cross products so that one
 // division serves all three weights.
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (relative error near one ulp); used where correct rounding is not required.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e,
                                         double eps) {
   const double q0 = (3.0 * a - 10.0 * b + 15.0 * c) * 0.125;
@@ -216,7 +227,7 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
   const double a0 = (1.0 / 16.0) * (t1 * t2);
   const double a1 = (10.0 / 16.0) * (t0 * t2);
   const double a2 = (5.0 / 16.0) * (t0 * t1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_nr(a0 + a1 + a2);
 }
 
 __device__ __forceinline__ double central4(double b, double c, double d, double e) {
@@ -232,7 +243,7 @@ struct EdgeState {
 template <int D, int J>
 __device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& w,
                                           double U[D + 2], double F[D + 2], double& speed) {
-  const double rho = w.p / w.T;
+  const double rho = w.p * rcp_nr(w.T);
   double uu = w.u[0] * w.u[0];
 #pragma unroll
   for (int i = 1; i < D; ++i) uu += w.u[i] * w.u[i];
@@ -301,7 +312,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
-    const double r = 1.0 / u[0];
+    const double r = rcp_nr(u[0]);
     double ke = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -807,6 +818,14 @@ __global__ __launch_bounds__(256) void k_prolong_new(DevMesh m, double* __restri
   }
 }
 
+__global__ void k_count_nonzero(const uint8_t* __restrict__ a, int n, int* __restrict__ out) {
+  int c = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    c += a[i] ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
 __global__ void k_scatter_int(int* __restrict__ dst, const int* __restrict__ pairs, int npairs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < npairs) dst[pairs[2 * i]] = pairs[2 * i + 1];
@@ -947,6 +966,12 @@ void Kernels::prolong_new(const DevMesh& m, double* U, const int* list, int coun
                           hipStream_t s) {
   if (count <= 0) return;
   AMR_DISPATCH_DIM(m.dim, k_prolong_new, dim3(count), dim3(256), s, m, U, list, count, err);
+}
+
+void Kernels::count_nonzero(const uint8_t* a, int n, int* out, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = std::min(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_count_nonzero, dim3(blocks), dim3(256), 0, s, a, n, out);
 }
 
 void Kernels::scatter_int(int* dst, const int* pairs, int npairs, hipStream_t s) {

@@ -1,0 +1,226 @@
+"""Learned refinement predictor: training data, training loop and the
+regridding policies that use it.  Every numerical step runs in libamr
+(gather, forward, backward, Adam, tagging, regridding); this module only
+sequences calls and moves small host-side arrays.
+
+Labels come from the solver itself: for a patch at step t, a cell is positive
+when the plain gradient tagger tags it (after dilation) at any step in
+(t, t + horizon].  Training data are recorded on single-level periodic runs
+of the 2D quadrant + blob generator at several resolutions, so that the
+network sees features at the cell sizes of several AMR levels.
+
+Policies (wall-clock per unit simulated time is the figure of merit):
+  plain  -- gradient tagging + regrid every ``every`` steps;
+  learned -- every ``every`` steps regrid with refine = plain | predicted and
+             coarsen = plain & predicted; at every step the plain tagger judges
+             the mesh and an immediate plain regrid follows when any tag is
+             uncovered (the fallback).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import amr as A
+from . import workloads as W
+
+
+def uniform_config(base: int, n: int = 32, tag_buffer: int = 2, cfl: float = 0.5,
+                   max_patches: int = 4096) -> W.AMRConfig:
+    return W.AMRConfig(name=f"uniform{base}", dim=2, base_cells=base, patch_cells=[n],
+                       periodic=[True, True], cfl=cfl, tag_buffer=tag_buffer,
+                       ic="quadrants_blobs", max_patches=max_patches, regrid_interval=0)
+
+
+def _cell_tags(h: A.Hierarchy, cells, pids: Sequence[int], n: int) -> np.ndarray:
+    flat = cells.cpu().numpy()
+    out = np.zeros((len(pids), n * n), np.uint8)
+    for b, pid in enumerate(pids):
+        off = h.offset(pid) // h.nvar
+        box = flat[off:off + (n + 8) ** 2].reshape(n + 8, n + 8)
+        out[b] = box[4:-4, 4:-4].ravel()
+    return out
+
+
+def record(cfg: W.AMRConfig, seed: int, steps: int, horizon: int, stride: int,
+           mean, std):
+    """Input tiles (device, BF16 bits) and labels (host) of one uniform run."""
+    torch = A._torch()
+    h = A.Hierarchy(cfg)
+    A.init_from_ic(h, W.initial_data(cfg, seed))
+    n = cfg.patch_cells[0]
+    pred = A.Predictor(h, n, mean, std, max_batch=1)
+    pids = [r["pid"] for r in h.patch_table()]
+    xs, tags = [], []
+    snaps = []
+    for t in range(steps + horizon + 1):
+        if t < steps and t % stride == 0:
+            xs.append(pred.gather(0, pids))
+            snaps.append(t)
+        _, _, cells = h.tag(0, cell_tags=True)
+        tags.append(_cell_tags(h, cells, pids, n))
+        h.step()
+    ys = []
+    for t in snaps:
+        y = np.zeros_like(tags[0])
+        for s in range(t + 1, t + horizon + 1):
+            y |= tags[s]
+        ys.append(y)
+    pred.close()
+    h.close()
+    return torch.cat(xs), np.concatenate(ys)
+
+
+def input_statistics(cfgs, seeds, steps=16):
+    """Per-channel mean and standard deviation of (rho, u, v, p) over the
+    recorded pixels (inputs gathered without normalisation)."""
+    vals = []
+    for cfg in cfgs:
+        for seed in seeds:
+            x, _ = record(cfg, seed, steps, horizon=1, stride=4, mean=(0, 0, 0, 0), std=(1, 1, 1, 1))
+            u = x.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+            vals.append(u.view(np.float32).reshape(-1, 4))
+    v = np.concatenate(vals).astype(np.float64)
+    return v.mean(axis=0), np.maximum(v.std(axis=0), 1e-3)
+
+
+@dataclasses.dataclass
+class Dataset:
+    x: object            # torch int16 [S, (n+6)^2, 4] on the device
+    y: np.ndarray        # uint8 [S, n^2]
+    n: int
+
+
+def build_dataset(resolutions: Sequence[int], seeds: Sequence[int], steps: int, horizon: int,
+                  stride: int, mean, std, n: int = 32) -> Dataset:
+    torch = A._torch()
+    xs, ys = [], []
+    for base in resolutions:
+        cfg = uniform_config(base, n)
+        for seed in seeds:
+            x, y = record(cfg, seed, steps, horizon, stride, mean, std)
+            xs.append(x)
+            ys.append(y)
+    return Dataset(torch.cat(xs), np.concatenate(ys), n)
+
+
+def train(pred: A.Predictor, data: Dataset, epochs: int, lr: float, batch: int, seed: int = 0,
+          log=None) -> List[float]:
+    torch = A._torch()
+    rng = np.random.default_rng(seed)
+    S = data.x.shape[0]
+    ydev = torch.from_numpy(data.y).to(data.x.device)
+    losses = []
+    for ep in range(epochs):
+        perm = rng.permutation(S)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, S - batch + 1, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).to(data.x.device)
+            loss = pred.train_step(data.x.index_select(0, idx).contiguous(),
+                                   ydev.index_select(0, idx).contiguous(), lr)
+            tot += loss.item()
+            cnt += 1
+        losses.append(tot / max(1, cnt))
+        if log:
+            log(f"epoch {ep}: loss {losses[-1]:.4f}")
+    return losses
+
+
+def patch_scores(pred: A.Predictor, x) -> np.ndarray:
+    """Max logit per patch."""
+    out = []
+    for b0 in range(0, x.shape[0], pred.max_batch):
+        z = pred.forward(x[b0:b0 + pred.max_batch].contiguous())
+        out.append(z.max(dim=1).values.cpu().numpy())
+    return np.concatenate(out)
+
+
+def choose_tau(pred: A.Predictor, data: Dataset, recall: float = 0.995) -> float:
+    """Probability threshold flagging at least `recall` of the patches that
+    have a positive cell."""
+    s = patch_scores(pred, data.x)
+    pos = data.y.reshape(data.y.shape[0], -1).any(axis=1)
+    if not pos.any():
+        return 0.5
+    zs = np.sort(s[pos])
+    k = int(math.floor((1.0 - recall) * len(zs)))
+    zt = zs[k] - 1e-3
+    return float(1.0 / (1.0 + math.exp(-zt)))
+
+
+def patch_metrics(pred: A.Predictor, data: Dataset, tau: float) -> Dict[str, float]:
+    s = patch_scores(pred, data.x)
+    zt = math.log(tau / (1.0 - tau))
+    flag = s > zt
+    pos = data.y.reshape(data.y.shape[0], -1).any(axis=1)
+    tp = int((flag & pos).sum())
+    return {"recall": tp / max(1, int(pos.sum())), "flagged": float(flag.mean()),
+            "positive": float(pos.mean())}
+
+
+# ---------------------------------------------------------------------------
+# regridding policies
+# ---------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class RunStats:
+    policy: str
+    steps: int
+    wall_s: float
+    t_sim: float
+    regrids: int
+    fallbacks: int
+    uncovered_steps: int
+    cell_updates: int
+
+    @property
+    def wall_per_tsim(self) -> float:
+        return self.wall_s / self.t_sim if self.t_sim > 0 else float("inf")
+
+    def as_dict(self):
+        d = dataclasses.asdict(self)
+        d["wall_per_tsim"] = self.wall_per_tsim
+        d["coverage"] = 1.0 - self.uncovered_steps / max(1, self.steps)
+        return d
+
+
+def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
+               pred: Optional[A.Predictor] = None, tau: float = 0.5,
+               judge: bool = False) -> RunStats:
+    """Advance `steps` steps under a regrid policy; wall time includes
+    tagging, prediction, judging and regridding."""
+    torch = A._torch()
+    dt = torch.zeros(1, dtype=torch.float64, device=h.device)
+    tsim = torch.zeros(1, dtype=torch.float64, device=h.device)
+    regrids = fallbacks = uncovered = cells = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(1, steps + 1):
+        cells += h.leaf_cells()
+        h.step(dt)
+        tsim += dt
+        if judge:
+            unc = h.judge()
+            if unc:
+                uncovered += 1
+                if policy == "learned":
+                    h.adapt()
+                    fallbacks += 1
+        if every > 0 and s % every == 0:
+            regrids += 1
+            if policy == "plain":
+                h.adapt()
+            else:
+                pr, pc = pred.predict(0, tau)
+                tr, tc, _ = h.tag(0)
+                r = (pr | tr).cpu().numpy()
+                c = (pc & tc).cpu().numpy()
+                h.regrid(r, c)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells)

@@ -117,3 +117,11 @@ def rel_linf(got: dict, ref: dict, keys, d, region="interior"):
             num[v] = max(num[v], float(np.max(np.abs(g[v] - r[v]))))
             den[v] = max(den[v], float(np.max(np.abs(r[v]))))
     return float(np.max(num / np.where(den > 0, den, 1.0)))
+
+
+def mirror_case(name: str, amr):
+    """Oracle hierarchy of a named case and its mirror in a new library hierarchy."""
+    o, _ = oracle_for(name)
+    h = amr.Hierarchy(o.cfg)
+    pid_of, key_of = mirror(o, h)
+    return o, h, pid_of, key_of
