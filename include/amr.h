@@ -270,6 +270,17 @@ amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_d
 amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const uint16_t* b_dev,
                                  float* d_dev);
 
+/* hipGraph replay of amr_step in batched mode (default on): the kernels of
+ * one step are captured once and replayed until the next regrid or mode
+ * change; the graph holds kernel nodes only.  Results are identical. */
+amr_status amr_set_graph(amr_hierarchy* h, int enable);
+
+/* Halo source of the fused stage kernel: 1 (default) gathers halo nodes
+ * outside a patch directly from same-level neighbours or by prolongation
+ * (the ghost-fill rule, no separate fill pass); 0 runs the fill kernel first
+ * and reads the filled ghost layers.  Results are identical. */
+amr_status amr_set_fused_halo(amr_hierarchy* h, int enable);
+
 #ifdef __cplusplus
 }
 #endif

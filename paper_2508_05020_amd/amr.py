@@ -108,6 +108,8 @@ _sigs = {
     "amr_cnn_predict": [_H, C.c_int, C.c_float, C.c_void_p, C.c_void_p],
     "amr_cnn_mfma_selftest": [_H, C.c_void_p, C.c_void_p, C.c_void_p],
     "amr_judge": [_H, _P(C.c_int)],
+    "amr_set_fused_halo": [_H, C.c_int],
+    "amr_set_graph": [_H, C.c_int],
     "amr_forest_replay": [_P(Config), _P(C.c_int32), C.c_int, _P(PatchInfo), C.c_int, _P(C.c_int)],
 }
 for _name, _args in _sigs.items():
@@ -379,6 +381,12 @@ class Hierarchy:
         ms, n, cells = C.c_double(), C.c_int(), C.c_int64()
         self._ok(_lib.amr_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells)))
         return ms.value, n.value, cells.value
+
+    def set_graph(self, enable: bool):
+        self._ok(_lib.amr_set_graph(self.h, 1 if enable else 0))
+
+    def set_fused_halo(self, enable: bool):
+        self._ok(_lib.amr_set_fused_halo(self.h, 1 if enable else 0))
 
     def judge(self) -> int:
         n = C.c_int()

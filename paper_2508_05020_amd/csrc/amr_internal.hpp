@@ -60,9 +60,11 @@ struct ListView {
 struct Kernels {
   static void fill(const DevMesh& m, double* U, const int* list, int count, int* err,
                    hipStream_t s);
+  // fuse = halo nodes outside the patch are gathered by the kernel itself
+  // (same rule as fill) instead of being read from filled ghost layers
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count,
-                    const double* lam, hipStream_t s);
+                    const double* lam, bool fuse, hipStream_t s);
   static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
                      const int* list, int count, const double* lam, double w,
                      hipStream_t s);

@@ -48,6 +48,13 @@ struct amr_hierarchy {
   std::string err;
   int nvar = 0;
   int exec_mode = AMR_EXEC_BATCHED;
+  bool fuse_halo = true;  // stage kernel gathers halos itself (no fill pass)
+  // hipGraph of one batched step (dt + 3 stages), valid until the next regrid
+  bool use_graph = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t step_exec = nullptr;
+  const double* step_exec_dt = nullptr;
+  bool step_exec_valid = false;
   std::vector<void*> owned;
 
   // device memory
@@ -120,6 +127,10 @@ struct amr_hierarchy {
     return p;
   }
   void release_all() {
+    if (step_exec) (void)hipGraphExecDestroy(step_exec);
+    step_exec = nullptr;
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    cap_stream = nullptr;
     if (h_stage) (void)hipHostFree(h_stage);
     h_stage = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -381,12 +392,13 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt) {
   static const int dst[4] = {0, 1, 2, 0};
   static const double w[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
   const int s = src[stage], d = dst[stage];
-  do_fill(h, s, h->leaves);
+  if (!h->fuse_halo) do_fill(h, s, h->leaves);
   const int tcells = ipow(h->dm.tile, h->cfg.dim);
   over_list(h, h->tiles, 2, [&](const int* p, int c) {
     hipEvent_t a{};
     if (h->profiling) h->prof_begin(&a);
-    Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->stream);
+    Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
+                   h->stream);
     if (h->profiling) h->prof_end((long long)c * tcells);
   });
   over_list(h, h->reflux, 2, [&](const int* p, int c) {
@@ -444,6 +456,7 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
     return AMR_E_MESH;
   }
   h->last_created = created;
+  h->step_exec_valid = false;
   sync_tables(h, false);
   // a missing prolongation source (impossible on a valid mesh) raises the
   // sticky error flag read by amr_fill_error; no synchronisation here
@@ -732,10 +745,10 @@ amr_status amr_fill_ghosts(amr_hierarchy* h, int buf) {
 amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
   if (!h || !buf_ok(buf) || !rhs_dev) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
-    do_fill(h, buf, h->leaves);
+    if (!h->fuse_halo) do_fill(h, buf, h->leaves);
     over_list(h, h->tiles, 2, [&](const int* p, int c) {
       Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, h->d_dt,
-                     h->stream);
+                     h->fuse_halo, h->stream);
     });
     over_list(h, h->reflux, 2, [&](const int* p, int c) {
       Kernels::reflux(h->dm, amr::kModeRHS, rhs_dev, h->fr, p, c, h->d_dt, 1.0, h->stream);
@@ -764,10 +777,47 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
   if (!h) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
     double* dt = dt_dev ? dt_dev : h->d_dt;
-    do_dt(h, 0, dt);
-    for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
+    const bool graph = h->use_graph && h->exec_mode == AMR_EXEC_BATCHED && !h->profiling;
+    if (!graph) {
+      do_dt(h, 0, dt);
+      for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
+      return AMR_OK;
+    }
+    if (!h->step_exec_valid || h->step_exec_dt != dt) {
+      if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      hipStream_t user = h->stream;
+      h->stream = h->cap_stream;
+      hipGraph_t g = nullptr;
+      HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        do_dt(h, 0, dt);
+        for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
+      } catch (...) {
+        (void)hipStreamEndCapture(h->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        h->stream = user;
+        throw;
+      }
+      HIP_OK(hipStreamEndCapture(h->stream, &g));
+      h->stream = user;
+      if (h->step_exec) HIP_OK(hipGraphExecDestroy(h->step_exec));
+      h->step_exec = nullptr;
+      const hipError_t e = hipGraphInstantiate(&h->step_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP_OK(e);
+      h->step_exec_valid = true;
+      h->step_exec_dt = dt;
+    }
+    HIP_OK(hipGraphLaunch(h->step_exec, h->stream));
     return AMR_OK;
   });
+}
+
+amr_status amr_set_graph(amr_hierarchy* h, int enable) {
+  if (!h) return AMR_E_ARG;
+  h->use_graph = enable != 0;
+  h->step_exec_valid = false;
+  return AMR_OK;
 }
 
 amr_status amr_tag(amr_hierarchy* h, int buf, uint8_t* refine_req_dev, uint8_t* coarsen_req_dev,
@@ -833,6 +883,14 @@ amr_status amr_judge(amr_hierarchy* h, int* uncovered) {
 amr_status amr_set_exec_mode(amr_hierarchy* h, int mode) {
   if (!h || (mode != AMR_EXEC_PER_PATCH && mode != AMR_EXEC_BATCHED)) return AMR_E_ARG;
   h->exec_mode = mode;
+  h->step_exec_valid = false;
+  return AMR_OK;
+}
+
+amr_status amr_set_fused_halo(amr_hierarchy* h, int enable) {
+  if (!h) return AMR_E_ARG;
+  h->fuse_halo = enable != 0;
+  h->step_exec_valid = false;
   return AMR_OK;
 }
 

@@ -279,10 +279,12 @@ struct TileShape {
       cmax(edges(0), cmax(D >= 2 ? edges(1) : 0, D >= 3 ? edges(2) : 0));
 };
 
-template <int D, int TX, int TY, int TZ, int NT, int J>
-__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Pin,
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE>
+__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
+                                                const double* __restrict__ Pin,
                                                 double* __restrict__ frp, int n, int full,
-                                                const int o[3], double* sP, double* sF,
+                                                const int o[3], const int pc[3], int l,
+                                                double* sP, double* sF,
                                                 double acc[][D + 2], double inv_h) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
@@ -308,10 +310,22 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     const int cx = o[0] + e0 - (J == 0 ? 4 : 0);
     const int cy = o[1] + e1 - (J == 1 ? 4 : 0);
     const int cz = o[2] + e2 - (J == 2 ? 4 : 0);
-    const long long off = box_off<D>(full, cx + NG, cy + NG, cz + NG);
     double u[NV];
+    const int cj = J == 0 ? cx : (J == 1 ? cy : cz);
+    if (!FUSE || (cj >= 0 && cj < n)) {
+      const long long off = box_off<D>(full, cx + NG, cy + NG, cz + NG);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+      for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+    } else {
+      // halo node outside the patch: the ghost-fill rule applied in place
+      int g[3] = {0, 0, 0};
+      const int c3[3] = {cx, cy, cz};
+      for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c3[j], m.lv[l].cells, m.periodic[j]);
+      bool ok = fetch_cell<D>(m, Uin, l, g, u);
+      if (!ok) ok = (l > 0) && prolong_cell<D>(m, Uin, l, g, u);
+      if (!ok)
+        for (int v = 0; v < NV; ++v) u[v] = __builtin_nan("");
+    }
     const double r = rcp_nr(u[0]);
     double ke = 0.0;
 #pragma unroll
@@ -408,7 +422,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
   __syncthreads();
 }
 
-template <int D, int TX, int TY, int TZ, int NT>
+template <int D, int TX, int TY, int TZ, int NT, bool FUSE>
 __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
@@ -436,11 +450,15 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
-  stage_direction<D, TX, TY, TZ, NT, 0>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  stage_direction<D, TX, TY, TZ, NT, 0, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
+                                              L.inv_h);
   if constexpr (D >= 2)
-    stage_direction<D, TX, TY, TZ, NT, 1>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+    stage_direction<D, TX, TY, TZ, NT, 1, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
+                                                L.inv_h);
   if constexpr (D >= 3)
-    stage_direction<D, TX, TY, TZ, NT, 2>(m, Pin, frp, n, full, o, sP, sF, acc, L.inv_h);
+    stage_direction<D, TX, TY, TZ, NT, 2, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
+                                                L.inv_h);
 
   const long long vs = var_stride<D>(full);
   const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
@@ -897,11 +915,17 @@ int Kernels::tiles_per_patch(int dim, int tile, int n) {
 
 void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count, const double* dt,
-                    hipStream_t s) {
+                    bool fuse, hipStream_t s) {
   if (count <= 0) return;
-#define AMR_STAGE(D, TX, TY, TZ, NT)                                                      \
-  hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT>), dim3(count), dim3(NT), 0, s, m, mode, Uin, \
-                     Un, out, fr, tiles, count, dt)
+#define AMR_STAGE(D, TX, TY, TZ, NT)                                                        \
+  do {                                                                                      \
+    if (fuse)                                                                               \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, true>), dim3(count), dim3(NT), 0, s, m, \
+                         mode, Uin, Un, out, fr, tiles, count, dt);                         \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, false>), dim3(count), dim3(NT), 0, s, m,\
+                         mode, Uin, Un, out, fr, tiles, count, dt);                         \
+  } while (0)
   if (m.dim == 1) {
     if (m.tile == 16) AMR_STAGE(1, 16, 1, 1, 64);
     else AMR_STAGE(1, 8, 1, 1, 64);

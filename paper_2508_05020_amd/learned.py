@@ -29,6 +29,16 @@ from . import amr as A
 from . import workloads as W
 
 
+def init_weights(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, in the flat parameter layout of the
+    library (W1 [16][4][3][3], b1, W2 [16][16][3][3], b2, W3 [16][3][3], b3)."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0.0, math.sqrt(2.0 / (4 * 9)), 16 * 4 * 9), np.zeros(16),
+             rng.normal(0.0, math.sqrt(2.0 / (16 * 9)), 16 * 16 * 9), np.zeros(16),
+             rng.normal(0.0, math.sqrt(2.0 / (16 * 9)), 16 * 9), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def uniform_config(base: int, n: int = 32, tag_buffer: int = 2, cfl: float = 0.5,
                    max_patches: int = 4096) -> W.AMRConfig:
     return W.AMRConfig(name=f"uniform{base}", dim=2, base_cells=base, patch_cells=[n],

@@ -294,3 +294,46 @@ def test_nonphysical_detected(amr):
     a[3, 6, 7] = -1.0  # negative total energy -> negative pressure
     h.set_state(0, {pid_of[k]: a})
     assert h.check() >= 1
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fused_halo_equals_explicit_fill_bitwise(name, amr):
+    o, h1, pid1, _ = _pair(name, amr)
+    _, h2, pid2, _ = _pair(name, amr)
+    h2.set_fused_halo(False)
+    for _ in range(2):
+        h1.step()
+        h2.step()
+    a = H.download(h1, 0, pid1)
+    b = H.download(h2, 0, pid2)
+    d = o.cfg.dim
+    for k in pid1:
+        assert np.array_equal(H.interior(a[k], d), H.interior(b[k], d)), k
+    r1 = H.tensor_patches(h1, h1.rhs(0), pid1)
+    r2 = H.tensor_patches(h2, h2.rhs(0), pid2)
+    for k in o.forest.leaves():
+        assert np.array_equal(H.interior(r1[k], d), H.interior(r2[k], d)), k
+
+
+@pytest.mark.parametrize("name", ["2d", "3d"])
+def test_graph_replays_equal_eager_bitwise(name, amr):
+    """Step graph (captured once, replayed until a regrid) against eager
+    launches: every replay, with eager work (tagging, regrids, host syncs) in
+    between, gives the eager result bit for bit."""
+    o, hg, pg, _ = _pair(name, amr)
+    _, he, pe, _ = _pair(name, amr)
+    he.set_graph(False)
+    d = o.cfg.dim
+    for s in range(1, 7):
+        hg.step()
+        he.step()
+        a = H.download(hg, 0, pg)
+        b = H.download(he, 0, pe)
+        for k in pg:
+            assert np.array_equal(H.interior(a[k], d), H.interior(b[k], d)), (s, k)
+        if s % 2 == 0:
+            hg.adapt()
+            he.adapt()
+            pg = {(t["level"], t["coord"]): t["pid"] for t in hg.patch_table()}
+            pe = {(t["level"], t["coord"]): t["pid"] for t in he.patch_table()}
+            assert set(pg) == set(pe)
