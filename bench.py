@@ -120,7 +120,7 @@ def learned_gain(args) -> int:
     results = {}
     steps = args.steps
     for name, every, buffer, policy in (("B2", 2, cfg.tag_buffer, "plain"),
-                                         ("B8", 8, 4, "plain"),
+                                         ("B8", 8, 3, "plain"),
                                          ("BL", 8, cfg.tag_buffer, "learned")):
         if policy == "learned":
             h = h_bl
@@ -161,6 +161,7 @@ def main() -> int:
     ap.add_argument("--exec", dest="exec_mode", default="batched", choices=["batched", "per_patch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--learned", action="store_true",
                     help="train the refinement predictor and compare regrid policies")
     ap.add_argument("--learned-config", default="c4")
@@ -189,6 +190,11 @@ def main() -> int:
     amr.init_from_ic(h, workloads.initial_data(cfg, args.seed))
     log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
         f"{h.leaf_cells()} leaf cells")
+    tile = None
+    if mode == amr.EXEC_BATCHED and not args.no_autotune:
+        best, best_ms = h.autotune(5)
+        tile = h.tile_variant()
+        log(f"[bench] autotuned tile variant {tile} ({best_ms * 1e3:.1f} us per RHS launch)")
 
     nstep = 0
 
@@ -255,6 +261,8 @@ def main() -> int:
                         f"{'periodic' if all(cfg.periodic) else 'mixed bc'}, ic {cfg.ic} "
                         f"seed {args.seed}, CFL {cfg.cfl}, regrid every {cfg.regrid_interval}",
             "exec": args.exec_mode,
+            "tile": None if tile is None else {"variant": tile[0], "extent": tile[1],
+                                               "threads": tile[2]},
             "leaf_cells_per_step_avg": cells / max(1, args.steps),
         },
         "roofline": {

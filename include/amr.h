@@ -275,6 +275,19 @@ amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const 
  * change; the graph holds kernel nodes only.  Results are identical. */
 amr_status amr_set_graph(amr_hierarchy* h, int enable);
 
+/* Tile variants of the fused stage kernel (cells per tile and block size):
+ * 0: 16 (1D, 64 threads), 1: 8 (1D), 2: 16x16 (2D, 320), 3: 16x8 (2D, 192),
+ * 4: 8x8 (2D, 128), 5: 8x8x8 (3D, 704), 6: 8x8x4 (3D, 448), 7: 4x4x4 (3D, 128).
+ * A variant is admissible when its extents divide every level's patch edge.
+ * Every variant performs the same operations per cell: results are
+ * identical.  amr_set_tile_variant (sync) selects one; amr_autotune (sync)
+ * times `reps` launches of each admissible variant on the current mesh
+ * (writing the stage buffer B and the flux registers) and keeps the fastest. */
+amr_status amr_set_tile_variant(amr_hierarchy* h, int variant);
+amr_status amr_get_tile_variant(const amr_hierarchy* h, int* variant, int* tx, int* ty, int* tz,
+                                int* threads);
+amr_status amr_autotune(amr_hierarchy* h, int reps, int* best, float* best_ms);
+
 /* Halo source of the fused stage kernel: 1 (default) gathers halo nodes
  * outside a patch directly from same-level neighbours or by prolongation
  * (the ghost-fill rule, no separate fill pass); 0 runs the fill kernel first

@@ -110,6 +110,9 @@ _sigs = {
     "amr_judge": [_H, _P(C.c_int)],
     "amr_set_fused_halo": [_H, C.c_int],
     "amr_set_graph": [_H, C.c_int],
+    "amr_set_tile_variant": [_H, C.c_int],
+    "amr_get_tile_variant": [_H, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)],
+    "amr_autotune": [_H, C.c_int, _P(C.c_int), _P(C.c_float)],
     "amr_forest_replay": [_P(Config), _P(C.c_int32), C.c_int, _P(PatchInfo), C.c_int, _P(C.c_int)],
 }
 for _name, _args in _sigs.items():
@@ -381,6 +384,20 @@ class Hierarchy:
         ms, n, cells = C.c_double(), C.c_int(), C.c_int64()
         self._ok(_lib.amr_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells)))
         return ms.value, n.value, cells.value
+
+    def set_tile_variant(self, v: int):
+        self._ok(_lib.amr_set_tile_variant(self.h, v))
+
+    def tile_variant(self):
+        v, x, y, z, t = (C.c_int() for _ in range(5))
+        self._ok(_lib.amr_get_tile_variant(self.h, C.byref(v), C.byref(x), C.byref(y), C.byref(z),
+                                           C.byref(t)))
+        return v.value, (x.value, y.value, z.value), t.value
+
+    def autotune(self, reps: int = 5):
+        b, ms = C.c_int(), C.c_float()
+        self._ok(_lib.amr_autotune(self.h, reps, C.byref(b), C.byref(ms)))
+        return b.value, ms.value
 
     def set_graph(self, enable: bool):
         self._ok(_lib.amr_set_graph(self.h, 1 if enable else 0))

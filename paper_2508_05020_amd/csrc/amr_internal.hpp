@@ -36,7 +36,7 @@ struct LevelC {
 // Everything a kernel needs to address patch data, passed by value.
 struct DevMesh {
   int dim, nvar, nlev, scheme;
-  int tile;           // tile edge of the fused stage kernel (cells)
+  int tile;           // stage-kernel tile variant (index into Kernels::variant)
   int periodic[3];
   int max_patches, maxc;
   double gamma, gm1, igm1, eps, theta, cfl;
@@ -62,19 +62,23 @@ struct Kernels {
                    hipStream_t s);
   // fuse = halo nodes outside the patch are gathered by the kernel itself
   // (same rule as fill) instead of being read from filled ghost layers
+  // lam_next (nullable, stage 3 only): accumulate the next step's CFL rate
+  // over leaf cells not on coarse/fine faces (cfmask: per-pid face bits)
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count,
-                    const double* lam, bool fuse, hipStream_t s);
+                    const double* dt, bool fuse, unsigned long long* lam_next,
+                    const uint8_t* cfmask, hipStream_t s);
   static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
-                     const int* list, int count, const double* lam, double w,
-                     hipStream_t s);
+                     const int* list, int count, const double* dt, double w,
+                     unsigned long long* lam_next, hipStream_t s);
   static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
                              hipStream_t s);
   static void max_rate(const DevMesh& m, const double* U, const int* list, int count,
                        unsigned long long* lam_bits, hipStream_t s);
   static void zero_u64(unsigned long long* p, hipStream_t s);
+  // dt = cfl / rate; also zeroes *clear (nullable), the next rate accumulator
   static void dt_from_rate(const DevMesh& m, const unsigned long long* lam_bits,
-                           double* dt, hipStream_t s);
+                           double* dt, unsigned long long* clear, hipStream_t s);
   static void tag(const DevMesh& m, const double* U, const int* list, int count,
                   uint8_t* has_tag, uint8_t* raw, hipStream_t s);
   static void cell_tags(const DevMesh& m, const uint8_t* raw, const int* list, int count,
@@ -87,9 +91,17 @@ struct Kernels {
   static void count_nonzero(const uint8_t* a, int n, int* out, hipStream_t s);
   static void check(const DevMesh& m, const double* U, const int* list, int count,
                     int* bad, hipStream_t s);
-  // Largest supported tile edge dividing every level's patch edge (0: none).
-  static int choose_tile(int dim, const int* n, int nlev);
-  static int tiles_per_patch(int dim, int tile, int n);
+  // Tile variants of the stage kernel: extents (cells) and block size.
+  struct TileVariant {
+    int dim, tx, ty, tz, threads;
+  };
+  static int num_variants();
+  static TileVariant variant(int v);
+  // Whether variant v fits every level's patch edge.
+  static bool variant_fits(int v, int dim, const int* n, int nlev);
+  // First fitting variant of a dimension (the default), -1 when none fits.
+  static int default_variant(int dim, const int* n, int nlev);
+  static int tiles_per_patch(int v, int n);
 };
 
 // Stage modes of the fused RHS/combine kernel.

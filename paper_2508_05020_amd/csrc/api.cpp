@@ -49,12 +49,19 @@ struct amr_hierarchy {
   int nvar = 0;
   int exec_mode = AMR_EXEC_BATCHED;
   bool fuse_halo = true;  // stage kernel gathers halos itself (no fill pass)
-  // hipGraph of one batched step (dt + 3 stages), valid until the next regrid
+  // hipGraphs of one batched step (dt + 3 stages), one per parity of the CFL
+  // rate double buffer, valid until the next regrid or mode change
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t step_exec = nullptr;
-  const double* step_exec_dt = nullptr;
+  hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+  const double* step_exec_dt[2] = {nullptr, nullptr};
   bool step_exec_valid = false;
+  bool step_exec_ok[2] = {false, false};
+  // CFL rate of U^n: slot lam_cur holds it when lam_valid; the step being
+  // run accumulates the next one into the other slot (slot 2: amr_compute_dt)
+  int lam_cur = 0;
+  bool lam_valid = false;
+  uint8_t* d_cfmask = nullptr;
   std::vector<void*> owned;
 
   // device memory
@@ -127,8 +134,10 @@ struct amr_hierarchy {
     return p;
   }
   void release_all() {
-    if (step_exec) (void)hipGraphExecDestroy(step_exec);
-    step_exec = nullptr;
+    for (int k = 0; k < 2; ++k) {
+      if (step_exec[k]) (void)hipGraphExecDestroy(step_exec[k]);
+      step_exec[k] = nullptr;
+    }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
     if (h_stage) (void)hipHostFree(h_stage);
@@ -173,7 +182,7 @@ void validate_config(const amr_config& c) {
   }
   for (int j = 0; j < c.dim; ++j)
     if (c.periodic[j] != 0 && c.periodic[j] != 1) throw ArgError("periodic flags are 0 or 1");
-  if (!Kernels::choose_tile(c.dim, c.patch_cells, c.max_levels))
+  if (Kernels::default_variant(c.dim, c.patch_cells, c.max_levels) < 0)
     throw ArgError("patch edges must be multiples of 8 (1D, 2D) or 4 (3D)");
 }
 
@@ -185,7 +194,7 @@ void build_devmesh(amr_hierarchy* h) {
   m.nvar = c.dim + 2;
   m.nlev = c.max_levels;
   m.scheme = c.scheme;
-  m.tile = Kernels::choose_tile(c.dim, c.patch_cells, c.max_levels);
+  m.tile = Kernels::default_variant(c.dim, c.patch_cells, c.max_levels);
   for (int j = 0; j < 3; ++j) m.periodic[j] = j < c.dim ? c.periodic[j] : 1;
   m.max_patches = c.max_patches;
   m.maxc = f.maxc;
@@ -291,7 +300,7 @@ void sync_tables(amr_hierarchy* h, bool full) {
   for (int pid : order) {
     if (!f.is_leaf(pid)) continue;
     h->leaf_cells += ipow(f.n[f.level[pid]], f.dim);
-    const int nt = Kernels::tiles_per_patch(f.dim, h->dm.tile, f.n[f.level[pid]]);
+    const int nt = Kernels::tiles_per_patch(h->dm.tile, f.n[f.level[pid]]);
     for (int t = 0; t < nt; ++t) {
       L.push_back(pid);
       L.push_back(t);
@@ -355,6 +364,10 @@ void sync_tables(amr_hierarchy* h, bool full) {
     h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
   }
   HIP_OK(hipMemcpyAsync(h->d_active_leaf, sa, mp, hipMemcpyHostToDevice, h->stream));
+  uint8_t* sm = sa + mp;
+  std::fill(sm, sm + mp, (uint8_t)0);
+  for (int i = 0; i < nref; ++i) sm[L[r0 + 2 * i]] = (uint8_t)L[r0 + 2 * i + 1];
+  HIP_OK(hipMemcpyAsync(h->d_cfmask, sm, mp, hipMemcpyHostToDevice, h->stream));
   if (np > 0) {
     HIP_OK(hipMemcpyAsync(h->d_pairs, sp, pairs.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
@@ -387,33 +400,52 @@ void do_restrict(amr_hierarchy* h, int buf) {
     });
 }
 
-void do_stage(amr_hierarchy* h, int stage, const double* dt) {
+void do_stage(amr_hierarchy* h, int stage, const double* dt,
+              unsigned long long* lam_next = nullptr) {
   static const int src[4] = {0, 0, 1, 2};
   static const int dst[4] = {0, 1, 2, 0};
   static const double w[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
   const int s = src[stage], d = dst[stage];
   if (!h->fuse_halo) do_fill(h, s, h->leaves);
-  const int tcells = ipow(h->dm.tile, h->cfg.dim);
+  const Kernels::TileVariant tv = Kernels::variant(h->dm.tile);
+  const int tcells = tv.tx * tv.ty * tv.tz;
   over_list(h, h->tiles, 2, [&](const int* p, int c) {
     hipEvent_t a{};
     if (h->profiling) h->prof_begin(&a);
     Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
-                   h->stream);
+                   stage == 3 ? lam_next : nullptr, h->d_cfmask, h->stream);
     if (h->profiling) h->prof_end((long long)c * tcells);
   });
   over_list(h, h->reflux, 2, [&](const int* p, int c) {
-    Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage], h->stream);
+    Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage],
+                    stage == 3 ? lam_next : nullptr, h->stream);
   });
   do_restrict(h, d);
 }
 
-void do_dt(amr_hierarchy* h, int buf, double* dt) {
-  Kernels::zero_u64(h->d_lam, h->stream);
+// CFL rate of the leaf cells of buffer `buf` into rate slot `slot`
+void do_rate(amr_hierarchy* h, int buf, int slot) {
+  Kernels::zero_u64(h->d_lam + slot, h->stream);
   over_list(h, h->leaves, 1, [&](const int* p, int c) {
-    Kernels::max_rate(h->dm, h->U[buf], p, c, h->d_lam, h->stream);
+    Kernels::max_rate(h->dm, h->U[buf], p, c, h->d_lam + slot, h->stream);
   });
-  Kernels::dt_from_rate(h->dm, h->d_lam, dt, h->stream);
   h->check_launch();
+}
+
+void do_dt(amr_hierarchy* h, int buf, double* dt) {
+  do_rate(h, buf, 2);
+  Kernels::dt_from_rate(h->dm, h->d_lam + 2, dt, nullptr, h->stream);
+  h->check_launch();
+}
+
+// one step: dt from the current rate slot, three stages; stage 3 and its
+// flux correction accumulate the rate of the new U^n into the other slot
+void do_step(amr_hierarchy* h, double* dt, int cur) {
+  Kernels::dt_from_rate(h->dm, h->d_lam + cur, dt, h->d_lam + (1 - cur), h->stream);
+  h->check_launch();
+  do_stage(h, 1, dt);
+  do_stage(h, 2, dt);
+  do_stage(h, 3, dt, h->d_lam + (1 - cur));
 }
 
 void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_t* cells) {
@@ -457,6 +489,7 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
   }
   h->last_created = created;
   h->step_exec_valid = false;
+  h->lam_valid = false;
   sync_tables(h, false);
   // a missing prolongation source (impossible on a valid mesh) raises the
   // sticky error flag read by amr_fill_error; no synchronisation here
@@ -538,6 +571,7 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->fr = (double*)h->dev_alloc(h->fr_doubles * sizeof(double));
     h->d_tab = (int*)h->dev_alloc(h->tab_ints * sizeof(int));
     h->d_active_leaf = (uint8_t*)h->dev_alloc(mp);
+    h->d_cfmask = (uint8_t*)h->dev_alloc(mp);
     h->d_has_tag = (uint8_t*)h->dev_alloc(mp);
     h->d_refine = (uint8_t*)h->dev_alloc(mp);
     h->d_coarsen = (uint8_t*)h->dev_alloc(mp);
@@ -545,16 +579,20 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->d_lam = (unsigned long long*)h->dev_alloc(64);
     h->d_dt = (double*)h->dev_alloc(64);
     h->d_flags = (int*)h->dev_alloc(64);
-    long long tiles = 0;
-    for (int l = 0; l < f.nlev; ++l)
-      tiles += (long long)f.cap[l] * Kernels::tiles_per_patch(cfg->dim, h->dm.tile, f.n[l]);
+    long long tiles = 0;  // the most tiles any fitting variant can need
+    for (int v = 0; v < Kernels::num_variants(); ++v) {
+      if (!Kernels::variant_fits(v, cfg->dim, cfg->patch_cells, cfg->max_levels)) continue;
+      long long t = 0;
+      for (int l = 0; l < f.nlev; ++l) t += (long long)f.cap[l] * Kernels::tiles_per_patch(v, f.n[l]);
+      tiles = std::max(tiles, t);
+    }
     h->lists_cap = 2 * tiles + 8 * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
     h->d_pairs = (int*)h->dev_alloc(h->pairs_cap * 2 * sizeof(int));
     h->h_stage_bytes = (size_t)h->lists_cap * sizeof(int) + (size_t)h->pairs_cap * 2 * sizeof(int) +
-                       (size_t)mp + 256;
+                       2 * (size_t)mp + 256;
     HIP_OK(hipHostMalloc((void**)&h->h_stage, h->h_stage_bytes, hipHostMallocDefault));
     HIP_OK(hipMemsetAsync(h->d_has_tag, 0, mp, h->stream));
     HIP_OK(hipMemsetAsync(h->fr, 0, h->fr_doubles * sizeof(double), h->stream));
@@ -656,6 +694,7 @@ amr_status amr_get_patch_table(const amr_hierarchy* h, amr_patch_info* out, int 
 amr_status amr_set_state(amr_hierarchy* h, int buf, const double* host, const int* pids,
                          int npatch) {
   if (!h || !buf_ok(buf) || (npatch > 0 && (!host || !pids))) return AMR_E_ARG;
+  h->lam_valid = false;
   return guarded(h, [&]() -> amr_status {
     long long pos = 0;
     for (int i = 0; i < npatch; ++i) {
@@ -693,6 +732,7 @@ amr_status amr_get_state(const amr_hierarchy* hc, int buf, double* host, const i
 amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* prim, const int* pids,
                               int npatch) {
   if (!h || !buf_ok(buf) || (npatch > 0 && (!prim || !pids))) return AMR_E_ARG;
+  h->lam_valid = false;
   return guarded(h, [&]() -> amr_status {
     const int d = h->cfg.dim, nv = h->nvar;
     const double gm1 = h->cfg.gamma - 1.0;
@@ -748,10 +788,10 @@ amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
     if (!h->fuse_halo) do_fill(h, buf, h->leaves);
     over_list(h, h->tiles, 2, [&](const int* p, int c) {
       Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, h->d_dt,
-                     h->fuse_halo, h->stream);
+                     h->fuse_halo, nullptr, h->d_cfmask, h->stream);
     });
     over_list(h, h->reflux, 2, [&](const int* p, int c) {
-      Kernels::reflux(h->dm, amr::kModeRHS, rhs_dev, h->fr, p, c, h->d_dt, 1.0, h->stream);
+      Kernels::reflux(h->dm, amr::kModeRHS, rhs_dev, h->fr, p, c, h->d_dt, 1.0, nullptr, h->stream);
     });
     return AMR_OK;
   });
@@ -767,6 +807,7 @@ amr_status amr_compute_dt(amr_hierarchy* h, int buf, double* dt_dev) {
 
 amr_status amr_rk_stage(amr_hierarchy* h, int stage, const double* dt_dev) {
   if (!h || stage < 1 || stage > 3 || !dt_dev) return AMR_E_ARG;
+  h->lam_valid = false;
   return guarded(h, [&]() -> amr_status {
     do_stage(h, stage, dt_dev);
     return AMR_OK;
@@ -777,38 +818,44 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
   if (!h) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
     double* dt = dt_dev ? dt_dev : h->d_dt;
+    const int cur = h->lam_cur;
+    if (!h->lam_valid) do_rate(h, 0, cur);
     const bool graph = h->use_graph && h->exec_mode == AMR_EXEC_BATCHED && !h->profiling;
     if (!graph) {
-      do_dt(h, 0, dt);
-      for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
-      return AMR_OK;
-    }
-    if (!h->step_exec_valid || h->step_exec_dt != dt) {
-      if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-      hipStream_t user = h->stream;
-      h->stream = h->cap_stream;
-      hipGraph_t g = nullptr;
-      HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      try {
-        do_dt(h, 0, dt);
-        for (int k = 1; k <= 3; ++k) do_stage(h, k, dt);
-      } catch (...) {
-        (void)hipStreamEndCapture(h->stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        h->stream = user;
-        throw;
+      do_step(h, dt, cur);
+    } else {
+      if (!h->step_exec_valid) {
+        h->step_exec_ok[0] = h->step_exec_ok[1] = false;
+        h->step_exec_valid = true;
       }
-      HIP_OK(hipStreamEndCapture(h->stream, &g));
-      h->stream = user;
-      if (h->step_exec) HIP_OK(hipGraphExecDestroy(h->step_exec));
-      h->step_exec = nullptr;
-      const hipError_t e = hipGraphInstantiate(&h->step_exec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIP_OK(e);
-      h->step_exec_valid = true;
-      h->step_exec_dt = dt;
+      if (!h->step_exec_ok[cur] || h->step_exec_dt[cur] != dt) {
+        if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = h->stream;
+        h->stream = h->cap_stream;
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        try {
+          do_step(h, dt, cur);
+        } catch (...) {
+          (void)hipStreamEndCapture(h->stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          h->stream = user;
+          throw;
+        }
+        HIP_OK(hipStreamEndCapture(h->stream, &g));
+        h->stream = user;
+        if (h->step_exec[cur]) HIP_OK(hipGraphExecDestroy(h->step_exec[cur]));
+        h->step_exec[cur] = nullptr;
+        const hipError_t e = hipGraphInstantiate(&h->step_exec[cur], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_OK(e);
+        h->step_exec_ok[cur] = true;
+        h->step_exec_dt[cur] = dt;
+      }
+      HIP_OK(hipGraphLaunch(h->step_exec[cur], h->stream));
     }
-    HIP_OK(hipGraphLaunch(h->step_exec, h->stream));
+    h->lam_cur = 1 - cur;
+    h->lam_valid = true;
     return AMR_OK;
   });
 }
@@ -885,6 +932,77 @@ amr_status amr_set_exec_mode(amr_hierarchy* h, int mode) {
   h->exec_mode = mode;
   h->step_exec_valid = false;
   return AMR_OK;
+}
+
+amr_status amr_set_tile_variant(amr_hierarchy* h, int variant) {
+  if (!h) return AMR_E_ARG;
+  if (!Kernels::variant_fits(variant, h->cfg.dim, h->cfg.patch_cells, h->cfg.max_levels))
+    return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    h->sync();
+    h->dm.tile = variant;
+    h->last_created.clear();
+    sync_tables(h, false);  // rebuilds the (pid, tile) list
+    h->step_exec_valid = false;
+    return AMR_OK;
+  });
+}
+
+amr_status amr_get_tile_variant(const amr_hierarchy* h, int* variant, int* tx, int* ty, int* tz,
+                                int* threads) {
+  if (!h || !variant) return AMR_E_ARG;
+  const Kernels::TileVariant t = Kernels::variant(h->dm.tile);
+  *variant = h->dm.tile;
+  if (tx) *tx = t.tx;
+  if (ty) *ty = t.ty;
+  if (tz) *tz = t.tz;
+  if (threads) *threads = t.threads;
+  return AMR_OK;
+}
+
+amr_status amr_autotune(amr_hierarchy* h, int reps, int* best, float* best_ms) {
+  if (!h || reps < 1) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    // time the stage kernel in RHS mode on U^n, writing into stage buffer B
+    // (scratch outside a step) and the flux registers
+    double* scratch = h->U[2];
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    const int orig = h->dm.tile;
+    int win = orig;
+    float win_ms = 1e30f;
+    for (int v = 0; v < Kernels::num_variants(); ++v) {
+      if (!Kernels::variant_fits(v, h->cfg.dim, h->cfg.patch_cells, h->cfg.max_levels)) continue;
+      h->dm.tile = v;
+      h->last_created.clear();
+      sync_tables(h, false);
+      Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->tiles.ptr,
+                     h->tiles.count, h->d_dt, h->fuse_halo, nullptr, h->d_cfmask, h->stream);
+      HIP_OK(hipEventRecord(e0, h->stream));
+      for (int r = 0; r < reps; ++r)
+        Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->tiles.ptr,
+                       h->tiles.count, h->d_dt, h->fuse_halo, nullptr, h->d_cfmask, h->stream);
+      HIP_OK(hipEventRecord(e1, h->stream));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (ms < win_ms) {
+        win_ms = ms;
+        win = v;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->dm.tile = win;
+    h->last_created.clear();
+    sync_tables(h, false);
+    h->step_exec_valid = false;
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return AMR_OK;
+  });
 }
 
 amr_status amr_set_fused_halo(amr_hierarchy* h, int enable) {

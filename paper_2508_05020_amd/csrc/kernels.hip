@@ -6,12 +6,13 @@
 // arrays built by the host after each regrid, so one launch covers the
 // patches of every level.
 //
-// Floating-point contract: the RHS/stage path may contract a*b+c into FMA
-// (its results are compared with the FP64 reference to a relative tolerance);
-// the prolongation, restriction, tag and time-step paths disable contraction
-// and use the same operation order as the definitions they implement, so
-// that integer decisions (tags, positivity switches) are taken on identical
-// values.
+// Floating-point contract: every kernel disables implicit contraction and
+// writes its fused multiply-adds out with fma(), so that a cell's operation
+// sequence is fixed by the source and identical in every kernel variant (tile
+// shape, fused or explicit halo, per-patch or batched launch).  The
+// prolongation, restriction, tag and time-step paths use the operation order
+// of the definitions they implement (no fma), so that integer decisions (tags,
+// positivity switches) are taken on the same values as the FP64 reference.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,6 +20,9 @@
 #include <cstdint>
 
 #include "amr_internal.hpp"
+
+// no implicit contraction anywhere in this file (see the header comment)
+#pragma clang fp contract(off)
 
 namespace amr {
 namespace {
@@ -84,7 +88,6 @@ __device__ bool fetch_cell(const DevMesh& m, const double* __restrict__ U, int l
 // u_j = m_j / rho, ke = 0.5 * (m_x u_x + m_y u_y + m_z u_z), p = (gamma-1)(E - ke).
 template <int D>
 __device__ __forceinline__ double pressure_exact(const double* u, double gm1) {
-#pragma clang fp contract(off)
   const double rho = u[0];
   double ke = u[1] * (u[1] / rho);
 #pragma unroll
@@ -99,7 +102,6 @@ __device__ __forceinline__ double pressure_exact(const double* u, double gm1) {
 template <int D>
 __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int lf,
                              const int g[3], double out[D + 2]) {
-#pragma clang fp contract(off)
   constexpr int NV = D + 2;
   const int lc = lf - 1;
   const LevelC& C = m.lv[lc];
@@ -148,6 +150,48 @@ __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int
     out[v] = x;
   }
   return true;
+}
+
+// CFL rate of one cell, sum_j (|u_j| + c) / h with c = sqrt(gamma p / rho),
+// as the IEEE bits of a non-negative double (order-preserving as an
+// unsigned integer); NaN maps to the largest value so that it propagates.
+template <int D>
+__device__ __forceinline__ unsigned long long cell_rate_bits(const double* u, const DevMesh& m,
+                                                             double h) {
+  const double rho = u[0];
+  double uj[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) uj[j] = u[1 + j] / rho;
+  double ke = u[1] * uj[0];
+#pragma unroll
+  for (int j = 1; j < D; ++j) ke = ke + u[1 + j] * uj[j];
+  ke = 0.5 * ke;
+  const double p = m.gm1 * (u[D + 1] - ke);
+  const double c = sqrt(m.gamma * p / rho);
+  double s = fabs(uj[0]) + c;
+#pragma unroll
+  for (int j = 1; j < D; ++j) s = s + (fabs(uj[j]) + c);
+  const double r = s / h;
+  if (!(r >= 0.0)) return 0x7ff8000000000000ull;
+  return (unsigned long long)__double_as_longlong(r);
+}
+
+// block-wide max of per-thread values, then one 64-bit atomic max
+__device__ __forceinline__ void block_max_atomic(unsigned long long best,
+                                                 unsigned long long* __restrict__ lam) {
+  __shared__ unsigned long long red[16];
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(best, off);
+    best = o > best ? o : best;
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = red[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = red[k] > b ? red[k] : b;
+    if (b) atomicMax(lam, b);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -211,27 +255,27 @@ __device__ __forceinline__ double rcp_nr(double x) {
 
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e,
                                         double eps) {
-  const double q0 = (3.0 * a - 10.0 * b + 15.0 * c) * 0.125;
-  const double q1 = (-b + 6.0 * c + 3.0 * d) * 0.125;
-  const double q2 = (3.0 * c + 6.0 * d - e) * 0.125;
-  const double k0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
-  const double k1 = b - 2.0 * c + d, s1 = b - d;
-  const double k2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
+  const double q0 = fma(15.0, c, fma(-10.0, b, 3.0 * a)) * 0.125;
+  const double q1 = fma(3.0, d, fma(6.0, c, -b)) * 0.125;
+  const double q2 = fma(6.0, d, fma(3.0, c, -e)) * 0.125;
+  const double k0 = fma(-2.0, b, a) + c, s0 = fma(3.0, c, fma(-4.0, b, a));
+  const double k1 = fma(-2.0, c, b) + d, s1 = b - d;
+  const double k2 = fma(-2.0, d, c) + e, s2 = fma(3.0, c, fma(-4.0, d, e));
   const double c1312 = 13.0 / 12.0;
-  const double b0 = c1312 * k0 * k0 + 0.25 * s0 * s0;
-  const double b1 = c1312 * k1 * k1 + 0.25 * s1 * s1;
-  const double b2 = c1312 * k2 * k2 + 0.25 * s2 * s2;
-  const double t0 = (eps + b0) * (eps + b0);
-  const double t1 = (eps + b1) * (eps + b1);
-  const double t2 = (eps + b2) * (eps + b2);
+  const double b0 = fma(c1312 * k0, k0, (0.25 * s0) * s0);
+  const double b1 = fma(c1312 * k1, k1, (0.25 * s1) * s1);
+  const double b2 = fma(c1312 * k2, k2, (0.25 * s2) * s2);
+  const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+  const double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
   const double a0 = (1.0 / 16.0) * (t1 * t2);
   const double a1 = (10.0 / 16.0) * (t0 * t2);
   const double a2 = (5.0 / 16.0) * (t0 * t1);
-  return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_nr(a0 + a1 + a2);
+  const double num = fma(a2, q2, fma(a1, q1, a0 * q0));
+  return num * rcp_nr((a0 + a1) + a2);
 }
 
 __device__ __forceinline__ double central4(double b, double c, double d, double e) {
-  return (9.0 * (c + d) - (b + e)) * 0.0625;
+  return fma(9.0, c + d, -(b + e)) * 0.0625;
 }
 
 template <int D>
@@ -246,15 +290,15 @@ __device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& 
   const double rho = w.p * rcp_nr(w.T);
   double uu = w.u[0] * w.u[0];
 #pragma unroll
-  for (int i = 1; i < D; ++i) uu += w.u[i] * w.u[i];
-  const double E = w.p * m.igm1 + 0.5 * rho * uu;
+  for (int i = 1; i < D; ++i) uu = fma(w.u[i], w.u[i], uu);
+  const double E = fma(0.5 * rho, uu, w.p * m.igm1);
   U[0] = rho;
   F[0] = rho * w.u[J];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const double mi = rho * w.u[i];
     U[1 + i] = mi;
-    F[1 + i] = mi * w.u[J] + (i == J ? w.p : 0.0);
+    F[1 + i] = (i == J) ? fma(mi, w.u[J], w.p) : mi * w.u[J];
   }
   U[D + 1] = E;
   F[D + 1] = (E + w.p) * w.u[J];
@@ -331,10 +375,10 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       const double ui = u[1 + i] * r;
-      ke += u[1 + i] * ui;
+      ke = (i == 0) ? u[1] * ui : fma(u[1 + i], ui, ke);
       sP[(2 + i) * NEXT + idx] = ui;
     }
-    const double p = m.gm1 * (u[D + 1] - 0.5 * ke);
+    const double p = m.gm1 * fma(-0.5, ke, u[D + 1]);
     sP[0 * NEXT + idx] = p;
     sP[1 * NEXT + idx] = p * r;
   }
@@ -378,7 +422,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     edge_flux<D, J>(m, wr, UR, FR, sr);
     const double S = fmax(sr, sl);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v * NED + e] = 0.5 * ((FR[v] + FL[v]) - S * (UR[v] - UL[v]));
+    for (int v = 0; v < NV; ++v) sF[v * NED + e] = 0.5 * fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
   }
   __syncthreads();
 
@@ -412,9 +456,9 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     for (int v = 0; v < NV; ++v) {
       const double* F = sF + v * NED + eb;
       const double Fm2 = F[0], Fm1 = F[ESTEP], F0 = F[2 * ESTEP], Fp1 = F[3 * ESTEP];
-      const double Gp = F0 - ((Fm1 - 2.0 * F0) + Fp1) * c24;
-      const double Gm = Fm1 - ((Fm2 - 2.0 * Fm1) + F0) * c24;
-      acc[cc][v] -= (Gp - Gm) * inv_h;
+      const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
+      const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
+      acc[cc][v] = fma(-(Gp - Gm), inv_h, acc[cc][v]);
       if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = Gm;
       if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = Gp;
     }
@@ -427,7 +471,9 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
                                               const int* __restrict__ tiles, int count,
-                                              const double* __restrict__ dtp) {
+                                              const double* __restrict__ dtp,
+                                              unsigned long long* __restrict__ lam_next,
+                                              const uint8_t* __restrict__ cfmask) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
@@ -463,6 +509,11 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
   const long long vs = var_stride<D>(full);
   const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
   constexpr double c23 = 2.0 / 3.0;
+  // next step's CFL rate from the final leaf values; cells on coarse/fine
+  // faces are left to the flux-correction kernel, which changes them
+  const bool want_rate = lam_next != nullptr && mode == kModeStage3;
+  const int fmask = want_rate ? cfmask[pid] : 0;
+  unsigned long long best = 0ull;
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int cell = threadIdx.x + cc * NT;
@@ -471,23 +522,34 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
     const int t1 = (cell / S::T0) % S::T1;
     const int t2 = cell / (S::T0 * S::T1);
     const long long off = base + box_off<D>(full, o[0] + t0 + NG, o[1] + t1 + NG, o[2] + t2 + NG);
+    double r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const long long a = off + v * vs;
       const double Lv = acc[cc][v];
-      double r;
       if (mode == kModeRHS) {
-        r = Lv;
+        r[v] = Lv;
       } else if (mode == kModeStage1) {
-        r = Un[a] + dt * Lv;
+        r[v] = fma(dt, Lv, Un[a]);
       } else {
         const double un = Un[a];
         const double ui = Uin[a];
-        r = un + (mode == kModeStage2 ? 0.25 : c23) * ((ui + dt * Lv) - un);
+        r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
-      out[a] = r;
+      out[a] = r[v];
+    }
+    if (want_rate) {
+      const int c3[3] = {o[0] + t0, o[1] + t1, o[2] + t2};
+      bool on_cf = false;
+      for (int j = 0; j < D; ++j)
+        on_cf |= ((fmask >> (2 * j)) & 1) && c3[j] == 0 || ((fmask >> (2 * j + 1)) & 1) && c3[j] == n - 1;
+      if (!on_cf) {
+        const unsigned long long bits = cell_rate_bits<D>(r, m, L.h);
+        best = bits > best ? bits : best;
+      }
     }
   }
+  if (want_rate) block_max_atomic(best, lam_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,7 +560,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_reflux(DevMesh m, int mode, double* __restrict__ out,
                                                 const double* __restrict__ fr,
                                                 const int* __restrict__ list, int count,
-                                                const double* __restrict__ dtp, double w) {
+                                                const double* __restrict__ dtp, double w,
+                                                unsigned long long* __restrict__ lam_next) {
   constexpr int NV = D + 2;
   if ((int)blockIdx.x >= count) return;
   const int pid = list[2 * blockIdx.x];
@@ -513,7 +576,7 @@ __global__ __launch_bounds__(256) void k_reflux(DevMesh m, int mode, double* __r
   const double* frc = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
   double* P = out + patch_base(m, pid, l);
   const long long vs = var_stride<D>(L.full);
-  const double coef = (mode == kModeRHS) ? L.inv_h : w * dtp[0] * L.inv_h;
+  const double coef = (mode == kModeRHS) ? L.inv_h : (w * dtp[0]) * L.inv_h;
   for (int f = 0; f < 2 * D; ++f) {
     if (mask & (1 << f)) {
       const int j = f >> 1, side = f & 1;
@@ -568,12 +631,34 @@ __global__ __launch_bounds__(256) void k_reflux(DevMesh m, int mode, double* __r
           else avg = ((sub[0][v] + sub[1][v]) + (sub[2][v] + sub[3][v])) * 0.25;
           if (!ok) avg = __builtin_nan("");
           const double gc = frc[((j * 2 + side) * NV + v) * nface + t];
-          P[v * vs + off] += coef * (sgn * (gc - avg));
+          P[v * vs + off] = fma(coef, sgn * (gc - avg), P[v * vs + off]);
         }
       }
     }
     __syncthreads();
   }
+  if (lam_next == nullptr || mode != kModeStage3) return;
+  // CFL rate of every corrected cell, from its final value
+  unsigned long long best = 0ull;
+  for (int f = 0; f < 2 * D; ++f) {
+    if (!(mask & (1 << f))) continue;
+    const int j = f >> 1, side = f & 1;
+    int tdim[2] = {0, 0}, nt = 0;
+    for (int k = 0; k < D; ++k)
+      if (k != j) tdim[nt++] = k;
+    for (int t = threadIdx.x; t < nface; t += blockDim.x) {
+      int c[3] = {0, 0, 0};
+      c[j] = side ? n - 1 : 0;
+      if constexpr (D >= 2) c[tdim[0]] = t % n;
+      if constexpr (D >= 3) c[tdim[1]] = t / n;
+      const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+      double u[NV];
+      for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
+      const unsigned long long bits = cell_rate_bits<D>(u, m, L.h);
+      best = bits > best ? bits : best;
+    }
+  }
+  block_max_atomic(best, lam_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,7 +668,6 @@ __global__ __launch_bounds__(256) void k_reflux(DevMesh m, int mode, double* __r
 template <int D>
 __global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
                                                   const int* __restrict__ list, int count) {
-#pragma clang fp contract(off)
   constexpr int NV = D + 2;
   if ((int)blockIdx.x >= count) return;
   const int cpid = list[blockIdx.x];
@@ -632,9 +716,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_max_rate(DevMesh m, const double* __restrict__ U,
                                                   const int* __restrict__ list, int count,
                                                   unsigned long long* __restrict__ lam) {
-#pragma clang fp contract(off)
   constexpr int NV = D + 2;
-  __shared__ unsigned long long red[4];
   unsigned long long best = 0ull;
   if ((int)blockIdx.x < count) {
     const int pid = list[blockIdx.x];
@@ -654,44 +736,19 @@ __global__ __launch_bounds__(256) void k_max_rate(DevMesh m, const double* __res
       double u[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
-      const double rho = u[0];
-      double uj[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) uj[j] = u[1 + j] / rho;
-      double ke = u[1] * uj[0];
-#pragma unroll
-      for (int j = 1; j < D; ++j) ke = ke + u[1 + j] * uj[j];
-      ke = 0.5 * ke;
-      const double p = m.gm1 * (u[D + 1] - ke);
-      const double c = sqrt(m.gamma * p / rho);
-      double s = fabs(uj[0]) + c;
-#pragma unroll
-      for (int j = 1; j < D; ++j) s = s + (fabs(uj[j]) + c);
-      const double r = s / L.h;
-      unsigned long long bits = (unsigned long long)__double_as_longlong(r);
-      if (!(r >= 0.0)) bits = 0x7ff8000000000000ull;  // NaN propagates as the maximum
+      const unsigned long long bits = cell_rate_bits<D>(u, m, L.h);
       best = bits > best ? bits : best;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long o = __shfl_xor(best, off);
-    best = o > best ? o : best;
-  }
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[wave] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long b = red[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = red[k] > b ? red[k] : b;
-    if (b) atomicMax(lam, b);
-  }
+  block_max_atomic(best, lam);
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { p[0] = 0ull; }
 
 __global__ void k_dt_from_rate(const unsigned long long* __restrict__ lam, double cfl,
-                               double* __restrict__ dt) {
+                               double* __restrict__ dt, unsigned long long* __restrict__ clear) {
   dt[0] = cfl / __longlong_as_double((long long)lam[0]);
+  if (clear) clear[0] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -713,7 +770,6 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
                                              const int* __restrict__ list, int count,
                                              uint8_t* __restrict__ has_tag,
                                              uint8_t* __restrict__ raw) {
-#pragma clang fp contract(off)
   if ((int)blockIdx.x >= count) return;
   const int pid = list[blockIdx.x];
   const int l = m.level[pid];
@@ -897,53 +953,76 @@ void Kernels::fill(const DevMesh& m, double* U, const int* list, int count, int*
   AMR_DISPATCH_DIM(m.dim, k_fill, dim3(count), dim3(256), s, m, U, list, count, err);
 }
 
-int Kernels::choose_tile(int dim, const int* n, int nlev) {
-  static const int cand[4][2] = {{0, 0}, {16, 8}, {16, 8}, {8, 4}};
-  for (int k = 0; k < 2; ++k) {
-    const int t = cand[dim][k];
-    bool ok = true;
-    for (int l = 0; l < nlev; ++l) ok = ok && (n[l] % t == 0);
-    if (ok) return t;
+// Stage-kernel tile variants: thread counts cover the edges of one
+// direction of the tile in one pass (multiples of 64).
+static const Kernels::TileVariant kVariants[] = {
+    {1, 16, 1, 1, 64}, {1, 8, 1, 1, 64},                                   // 1D
+    {2, 16, 16, 1, 320}, {2, 16, 8, 1, 192}, {2, 8, 8, 1, 128},           // 2D
+    {3, 8, 8, 8, 704}, {3, 8, 8, 4, 448}, {3, 4, 4, 4, 128},              // 3D
+};
+
+int Kernels::num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+Kernels::TileVariant Kernels::variant(int v) { return kVariants[v]; }
+
+bool Kernels::variant_fits(int v, int dim, const int* n, int nlev) {
+  if (v < 0 || v >= num_variants() || kVariants[v].dim != dim) return false;
+  const TileVariant& t = kVariants[v];
+  for (int l = 0; l < nlev; ++l) {
+    if (n[l] % t.tx) return false;
+    if (dim >= 2 && n[l] % t.ty) return false;
+    if (dim >= 3 && n[l] % t.tz) return false;
   }
-  return 0;
+  return true;
 }
 
-int Kernels::tiles_per_patch(int dim, int tile, int n) {
-  const int r = n / tile;
-  return dim == 1 ? r : (dim == 2 ? r * r : r * r * r);
+int Kernels::default_variant(int dim, const int* n, int nlev) {
+  for (int v = 0; v < num_variants(); ++v)
+    if (variant_fits(v, dim, n, nlev)) return v;
+  return -1;
+}
+
+int Kernels::tiles_per_patch(int v, int n) {
+  const TileVariant& t = kVariants[v];
+  int r = n / t.tx;
+  if (t.dim >= 2) r *= n / t.ty;
+  if (t.dim >= 3) r *= n / t.tz;
+  return r;
 }
 
 void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count, const double* dt,
-                    bool fuse, hipStream_t s) {
+                    bool fuse, unsigned long long* lam_next, const uint8_t* cfmask,
+                    hipStream_t s) {
   if (count <= 0) return;
 #define AMR_STAGE(D, TX, TY, TZ, NT)                                                        \
   do {                                                                                      \
     if (fuse)                                                                               \
       hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, true>), dim3(count), dim3(NT), 0, s, m, \
-                         mode, Uin, Un, out, fr, tiles, count, dt);                         \
+                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);       \
     else                                                                                    \
       hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, false>), dim3(count), dim3(NT), 0, s, m,\
-                         mode, Uin, Un, out, fr, tiles, count, dt);                         \
+                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);       \
   } while (0)
-  if (m.dim == 1) {
-    if (m.tile == 16) AMR_STAGE(1, 16, 1, 1, 64);
-    else AMR_STAGE(1, 8, 1, 1, 64);
-  } else if (m.dim == 2) {
-    if (m.tile == 16) AMR_STAGE(2, 16, 16, 1, 320);
-    else AMR_STAGE(2, 8, 8, 1, 128);
-  } else {
-    if (m.tile == 8) AMR_STAGE(3, 8, 8, 8, 704);
-    else AMR_STAGE(3, 4, 4, 4, 128);
+  switch (m.tile) {
+    case 0: AMR_STAGE(1, 16, 1, 1, 64); break;
+    case 1: AMR_STAGE(1, 8, 1, 1, 64); break;
+    case 2: AMR_STAGE(2, 16, 16, 1, 320); break;
+    case 3: AMR_STAGE(2, 16, 8, 1, 192); break;
+    case 4: AMR_STAGE(2, 8, 8, 1, 128); break;
+    case 5: AMR_STAGE(3, 8, 8, 8, 704); break;
+    case 6: AMR_STAGE(3, 8, 8, 4, 448); break;
+    default: AMR_STAGE(3, 4, 4, 4, 128); break;
   }
 #undef AMR_STAGE
 }
 
 void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
-                     const int* list, int count, const double* dt, double w, hipStream_t s) {
+                     const int* list, int count, const double* dt, double w,
+                     unsigned long long* lam_next, hipStream_t s) {
   if (count <= 0) return;
   AMR_DISPATCH_DIM(m.dim, k_reflux, dim3(count), dim3(256), s, m, mode, out, fr, list, count,
-                   dt, w);
+                   dt, w, lam_next);
 }
 
 void Kernels::restrict_level(const DevMesh& m, double* U, const int* list, int count,
@@ -963,8 +1042,8 @@ void Kernels::zero_u64(unsigned long long* p, hipStream_t s) {
 }
 
 void Kernels::dt_from_rate(const DevMesh& m, const unsigned long long* lam, double* dt,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_dt_from_rate, dim3(1), dim3(1), 0, s, lam, m.cfl, dt);
+                           unsigned long long* clear, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_from_rate, dim3(1), dim3(1), 0, s, lam, m.cfl, dt, clear);
 }
 
 void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,

@@ -113,10 +113,10 @@ CONFIGS = {
     # 2D quadrants + blobs on 512^2, 5 levels of 32^2 patches.
     "c4": _cfg(name="c4", dim=2, base_cells=512, patch_cells=[32] * 5,
                periodic=[True, True], steps=200, regrid_interval=8,
-               tag_buffer=4, ic="quadrants_blobs", max_patches=65536),
+               tag_buffer=2, ic="quadrants_blobs", max_patches=65536),
     # 3D blast waves + k^-2 density perturbations, base 256^3.
     "c5": _cfg(name="c5", dim=3, base_cells=256, patch_cells=[32, 16, 16, 8],
-               periodic=[True] * 3, steps=200, regrid_interval=8, tag_buffer=4,
+               periodic=[True] * 3, steps=200, regrid_interval=8, tag_buffer=2,
                ic="blasts_perturbed", max_patches=131072),
     # The paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2.
     "implosion": _cfg(name="implosion", dim=2, base_cells=256,

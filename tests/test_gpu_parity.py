@@ -337,3 +337,34 @@ def test_graph_replays_equal_eager_bitwise(name, amr):
             pg = {(t["level"], t["coord"]): t["pid"] for t in hg.patch_table()}
             pe = {(t["level"], t["coord"]): t["pid"] for t in he.patch_table()}
             assert set(pg) == set(pe)
+
+
+@pytest.mark.parametrize("name", ["2d", "3d", "3d-uneven"])
+def test_tile_variants_bitwise_and_autotune(name, amr):
+    """Every admissible tile shape gives the same result bit for bit (the
+    per-cell operation sequence does not depend on tiling), and the autotuner
+    picks one of them."""
+    import paper_2508_05020_amd.amr as A
+    o, _ = H.oracle_for(name)
+    d = o.cfg.dim
+    results = []
+    for v in range(8):
+        h = amr.Hierarchy(o.cfg)
+        pid, _ = H.mirror(o, h)
+        try:
+            h.set_tile_variant(v)
+        except A.AMRError:
+            h.close()
+            continue
+        h.step()
+        h.step()
+        results.append((v, H.download(h, 0, pid)))
+        if len(results) == 1:
+            best, ms = h.autotune(3)
+            assert best in range(8) and ms > 0
+        h.close()
+    assert len(results) >= 2
+    v0, ref = results[0]
+    for v, got in results[1:]:
+        for k in ref:
+            assert np.array_equal(H.interior(got[k], d), H.interior(ref[k], d)), (v, k)
