@@ -58,10 +58,13 @@ struct ListView {
 
 // Launch wrappers implemented in kernels.hip.
 struct Kernels {
+  // coarse_only: write only the ghost cells without a same-level source
+  // (the prolonged ones)
   static void fill(const DevMesh& m, double* U, const int* list, int count, int* err,
-                   hipStream_t s);
-  // fuse = halo nodes outside the patch are gathered by the kernel itself
-  // (same rule as fill) instead of being read from filled ghost layers
+                   bool coarse_only, hipStream_t s);
+  // fuse = halo nodes outside the patch with a same-level source are read
+  // from that source by the kernel itself; the others (prolonged) come from
+  // ghost layers filled by a coarse-only fill pass
   // lam_next (nullable, stage 3 only): accumulate the next step's CFL rate
   // over leaf cells not on coarse/fine faces (cfmask: per-pid face bits)
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,

@@ -93,7 +93,7 @@ struct amr_hierarchy {
 
   // host mirrors of the work lists
   std::vector<int> lists;
-  amr::ListView all{}, leaves{}, tiles{}, reflux{};
+  amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfleaves{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
   std::vector<int> last_created;
   std::vector<uint8_t> h_active_leaf;
@@ -295,6 +295,21 @@ void sync_tables(amr_hierarchy* h, bool full) {
   const int a1 = begin_list();
   for (int pid : order)
     if (f.is_leaf(pid)) L.push_back(pid);
+  const int c0 = begin_list();
+  for (int pid : order) {
+    if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
+    const int l = f.level[pid];
+    const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
+    bool missing = false;
+    for (const auto& off : f.moore()) {
+      int q[3];
+      if (f.shifted(l, c, off.data(), q) && f.lookup(l, q) < 0) {
+        missing = true;
+        break;
+      }
+    }
+    if (missing) L.push_back(pid);
+  }
   const int t0 = begin_list();
   h->leaf_cells = 0;
   for (int pid : order) {
@@ -356,7 +371,8 @@ void sync_tables(amr_hierarchy* h, bool full) {
     HIP_OK(hipMemcpyAsync(h->d_lists, sl, L.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
   h->all = {h->d_lists + a0, a1 - a0};
-  h->leaves = {h->d_lists + a1, t0 - a1};
+  h->leaves = {h->d_lists + a1, c0 - a1};
+  h->cfleaves = {h->d_lists + c0, t0 - c0};
   h->tiles = {h->d_lists + t0, (r0 - t0) / 2};
   h->reflux = {h->d_lists + r0, nref};
   for (int l = 0; l < f.nlev; ++l) {
@@ -387,10 +403,17 @@ void over_list(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F lau
   h->check_launch();
 }
 
-void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv) {
+void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_only = false) {
   over_list(h, lv, 1, [&](const int* p, int c) {
-    Kernels::fill(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+    Kernels::fill(h->dm, h->U[buf], p, c, h->d_flags, coarse_only, h->stream);
   });
+}
+
+// ghosts the stage kernel reads from memory: all of them, or with the fused
+// halo only the prolonged ones (leaves with a missing same-level neighbour)
+void stage_fill(amr_hierarchy* h, int buf) {
+  if (h->fuse_halo) do_fill(h, buf, h->cfleaves, true);
+  else do_fill(h, buf, h->leaves);
 }
 
 void do_restrict(amr_hierarchy* h, int buf) {
@@ -406,7 +429,7 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
   static const int dst[4] = {0, 1, 2, 0};
   static const double w[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
   const int s = src[stage], d = dst[stage];
-  if (!h->fuse_halo) do_fill(h, s, h->leaves);
+  stage_fill(h, s);
   const Kernels::TileVariant tv = Kernels::variant(h->dm.tile);
   const int tcells = tv.tx * tv.ty * tv.tz;
   over_list(h, h->tiles, 2, [&](const int* p, int c) {
@@ -586,7 +609,7 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
       for (int l = 0; l < f.nlev; ++l) t += (long long)f.cap[l] * Kernels::tiles_per_patch(v, f.n[l]);
       tiles = std::max(tiles, t);
     }
-    h->lists_cap = 2 * tiles + 8 * mp + 64;
+    h->lists_cap = 2 * tiles + 9 * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
@@ -785,7 +808,7 @@ amr_status amr_fill_ghosts(amr_hierarchy* h, int buf) {
 amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
   if (!h || !buf_ok(buf) || !rhs_dev) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
-    if (!h->fuse_halo) do_fill(h, buf, h->leaves);
+    stage_fill(h, buf);
     over_list(h, h->tiles, 2, [&](const int* p, int c) {
       Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, h->d_dt,
                      h->fuse_halo, nullptr, h->d_cfmask, h->stream);

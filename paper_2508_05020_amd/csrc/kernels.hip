@@ -200,7 +200,7 @@ __device__ __forceinline__ void block_max_atomic(unsigned long long best,
 template <int D>
 __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
                                               const int* __restrict__ list, int count,
-                                              int* __restrict__ err) {
+                                              int* __restrict__ err, int coarse_only) {
   constexpr int NV = D + 2;
   if ((int)blockIdx.x >= count) return;
   const int pid = list[blockIdx.x];
@@ -225,6 +225,7 @@ __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
     if (!ghost) continue;
     double val[NV];
     bool ok = fetch_cell<D>(m, U, l, g, val);
+    if (ok && coarse_only) continue;
     if (!ok) ok = (l > 0) && prolong_cell<D>(m, U, l, g, val);
     if (!ok) {
       err[0] = 1;
@@ -323,7 +324,70 @@ struct TileShape {
       cmax(edges(0), cmax(D >= 2 ? edges(1) : 0, D >= 3 ? edges(2) : 0));
 };
 
-template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE>
+// Primitives (p, T, u_j) of one node from its conserved values.
+template <int D>
+__device__ __forceinline__ void node_primitives(const DevMesh& m, const double* u, double* q) {
+  const double r = rcp_nr(u[0]);
+  double ke = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ui = u[1 + i] * r;
+    ke = (i == 0) ? u[1] * ui : fma(u[1 + i], ui, ke);
+    q[2 + i] = ui;
+  }
+  const double p = m.gm1 * fma(-0.5, ke, u[D + 1]);
+  q[0] = p;
+  q[1] = p * r;
+}
+
+// Conserved values of a node at patch-local cell c (may lie in the halo):
+// from the patch itself, or by the ghost-fill rule when outside the patch.
+template <int D, bool FUSE>
+__device__ __forceinline__ void node_conserved(const DevMesh& m, const double* __restrict__ Uin,
+                                               const double* __restrict__ Pin, int n, int full,
+                                               const int c[3], const int pc[3], int l,
+                                               double* u) {
+  constexpr int NV = D + 2;
+  bool inside = true;
+  for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
+  if (FUSE && !inside) {
+    int g[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c[j], m.lv[l].cells, m.periodic[j]);
+    if (fetch_cell<D>(m, Uin, l, g, u)) return;
+    // no same-level source: the prolonged ghost value was written into the
+    // patch's own ghost layer by the coarse-ghost fill pass
+  }
+  const long long vs = var_stride<D>(full);
+  const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+}
+
+// 1D/2D: primitives of the tile plus 4-node halos in every direction
+// (corner nodes, used by no stencil, are skipped), loaded once per launch.
+template <int D, int TX, int TY, int NT, bool FUSE>
+__device__ __forceinline__ void load_union(const DevMesh& m, const double* __restrict__ Uin,
+                                           const double* __restrict__ Pin, int n, int full,
+                                           const int o[3], const int pc[3], int l, double* sP) {
+  constexpr int T0 = TX, T1 = D >= 2 ? TY : 1;
+  constexpr int U0 = T0 + 8, U1 = D >= 2 ? T1 + 8 : 1;
+  constexpr int NU = U0 * U1;
+  constexpr int NQ = D + 2;
+  for (int idx = threadIdx.x; idx < NU; idx += NT) {
+    const int e0 = idx % U0, e1 = idx / U0;
+    const bool hx = e0 < 4 || e0 >= T0 + 4;
+    const bool hy = D >= 2 && (e1 < 4 || e1 >= T1 + 4);
+    if (hx && hy) continue;
+    const int c[3] = {o[0] + e0 - 4, D >= 2 ? o[1] + e1 - 4 : 0, 0};
+    double u[D + 2], q[NQ];
+    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
+    node_primitives<D>(m, u, q);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) sP[k * NU + idx] = q[k];
+  }
+}
+
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool UNION>
 __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
                                                 const double* __restrict__ Pin,
                                                 double* __restrict__ frp, int n, int full,
@@ -333,9 +397,9 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int NQ = D + 2;  // interpolated primitives: p, T, u_j
-  constexpr int E0 = S::T0 + (J == 0 ? 8 : 0);
-  constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
-  constexpr int E2 = S::T2 + (J == 2 ? 8 : 0);
+  constexpr int E0 = UNION ? S::T0 + 8 : S::T0 + (J == 0 ? 8 : 0);
+  constexpr int E1 = UNION ? (D >= 2 ? S::T1 + 8 : 1) : S::T1 + (J == 1 ? 8 : 0);
+  constexpr int E2 = UNION ? 1 : S::T2 + (J == 2 ? 8 : 0);
   constexpr int NEXT = E0 * E1 * E2;
   constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
   constexpr int G1 = S::T1 + (J == 1 ? 3 : 0);
@@ -343,53 +407,36 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
   constexpr int NED = G0 * G1 * G2;
   constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
-  const long long vs = var_stride<D>(full);
   const int tid = threadIdx.x;
 
   // 1. primitives of the tile extended by 4 nodes on both sides along J
-  for (int idx = tid; idx < NEXT; idx += NT) {
-    const int e0 = idx % E0;
-    const int e1 = (idx / E0) % E1;
-    const int e2 = idx / (E0 * E1);
-    const int cx = o[0] + e0 - (J == 0 ? 4 : 0);
-    const int cy = o[1] + e1 - (J == 1 ? 4 : 0);
-    const int cz = o[2] + e2 - (J == 2 ? 4 : 0);
-    double u[NV];
-    const int cj = J == 0 ? cx : (J == 1 ? cy : cz);
-    if (!FUSE || (cj >= 0 && cj < n)) {
-      const long long off = box_off<D>(full, cx + NG, cy + NG, cz + NG);
+  // (the union layout is loaded once by the caller for all directions)
+  if constexpr (!UNION) {
+    for (int idx = tid; idx < NEXT; idx += NT) {
+      const int e0 = idx % E0;
+      const int e1 = (idx / E0) % E1;
+      const int e2 = idx / (E0 * E1);
+      const int c[3] = {o[0] + e0 - (J == 0 ? 4 : 0), o[1] + e1 - (J == 1 ? 4 : 0),
+                        o[2] + e2 - (J == 2 ? 4 : 0)};
+      double u[NV], q[NQ];
+      node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
+      node_primitives<D>(m, u, q);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
-    } else {
-      // halo node outside the patch: the ghost-fill rule applied in place
-      int g[3] = {0, 0, 0};
-      const int c3[3] = {cx, cy, cz};
-      for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c3[j], m.lv[l].cells, m.periodic[j]);
-      bool ok = fetch_cell<D>(m, Uin, l, g, u);
-      if (!ok) ok = (l > 0) && prolong_cell<D>(m, Uin, l, g, u);
-      if (!ok)
-        for (int v = 0; v < NV; ++v) u[v] = __builtin_nan("");
+      for (int k = 0; k < NQ; ++k) sP[k * NEXT + idx] = q[k];
     }
-    const double r = rcp_nr(u[0]);
-    double ke = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const double ui = u[1 + i] * r;
-      ke = (i == 0) ? u[1] * ui : fma(u[1 + i], ui, ke);
-      sP[(2 + i) * NEXT + idx] = ui;
-    }
-    const double p = m.gm1 * fma(-0.5, ke, u[D + 1]);
-    sP[0 * NEXT + idx] = p;
-    sP[1 * NEXT + idx] = p * r;
+    __syncthreads();
   }
-  __syncthreads();
 
   // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
   for (int e = tid; e < NED; e += NT) {
     const int a0 = e % G0;
     const int a1 = (e / G0) % G1;
     const int a2 = e / (G0 * G1);
-    const int base = a0 + E0 * (a1 + E1 * a2);  // ext index of node i-2
+    // layout index of node i-2 of this edge's window
+    int base;
+    if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);
+    else if constexpr (J == 0) base = (D >= 2 ? (a1 + 4) * E0 : 0) + a0;
+    else base = a1 * E0 + (a0 + 4);
     EdgeState<D> wl, wr;
     double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
 #pragma unroll
@@ -477,7 +524,9 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
-  __shared__ double sP[(D + 2) * S::EXTMAX];
+  constexpr bool UNION = D <= 2;
+  constexpr int NU = (S::T0 + 8) * (D >= 2 ? S::T1 + 8 : 1);
+  __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
   __shared__ double sF[(D + 2) * S::EDMAX];
   if ((int)blockIdx.x >= count) return;
   const int pid = tiles[2 * blockIdx.x];
@@ -497,14 +546,18 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
-  stage_direction<D, TX, TY, TZ, NT, 0, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
-                                              L.inv_h);
+  if constexpr (UNION) {
+    load_union<D, TX, TY, NT, FUSE>(m, Uin, Pin, n, full, o, pc, l, sP);
+    __syncthreads();
+  }
+  stage_direction<D, TX, TY, TZ, NT, 0, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF,
+                                                     acc, L.inv_h);
   if constexpr (D >= 2)
-    stage_direction<D, TX, TY, TZ, NT, 1, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
-                                                L.inv_h);
+    stage_direction<D, TX, TY, TZ, NT, 1, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
+                                                       sF, acc, L.inv_h);
   if constexpr (D >= 3)
-    stage_direction<D, TX, TY, TZ, NT, 2, FUSE>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF, acc,
-                                                L.inv_h);
+    stage_direction<D, TX, TY, TZ, NT, 2, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
+                                                       sF, acc, L.inv_h);
 
   const long long vs = var_stride<D>(full);
   const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
@@ -948,9 +1001,10 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
   } while (0)
 
 void Kernels::fill(const DevMesh& m, double* U, const int* list, int count, int* err,
-                   hipStream_t s) {
+                   bool coarse_only, hipStream_t s) {
   if (count <= 0) return;
-  AMR_DISPATCH_DIM(m.dim, k_fill, dim3(count), dim3(256), s, m, U, list, count, err);
+  AMR_DISPATCH_DIM(m.dim, k_fill, dim3(count), dim3(256), s, m, U, list, count, err,
+                   coarse_only ? 1 : 0);
 }
 
 // Stage-kernel tile variants: thread counts cover the edges of one
