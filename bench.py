@@ -47,6 +47,38 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+COUNTERS = os.path.join(ROOT, "profiles", "k_stage_counters.json")
+KERNEL_SOURCES = ("paper_2508_05020_amd/csrc/kernels.hip", "paper_2508_05020_amd/csrc/amr_internal.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(variant, cells_per_launch):
+    """HBM bytes per stage-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy-kernel
+    calibration, per leaf cell of the launch), or None when the summary is
+    missing, was taken on another kernel source, or on another tile variant."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if variant is None or c.get("source_sha256") != kernel_source_hash():
+        return None
+    v = c.get("variants", {}).get(str(variant))
+    if not v:
+        return None
+    return (v["fetch_bytes_per_cell"] + v["write_bytes_per_cell"]) * cells_per_launch
+
+
 def cpu_baseline(cfg, seed: int):
     """The oracle, as it stands, on a bounded sample: one SSP-RK3 step over the
     initial hierarchy of the same workload."""
@@ -94,7 +126,7 @@ def learned_gain(args) -> int:
     seeds_train = list(range(4000, 4000 + args.train_runs))
     mean, std = learned.input_statistics([learned.uniform_config(128)], seeds_train[:2])
     log(f"[learned] input mean {np.round(mean, 3)} std {np.round(std, 3)}")
-    data = learned.build_dataset((128, 256), seeds_train, steps=40, horizon=8, stride=2,
+    data = learned.build_dataset((128, 256, 512), seeds_train, steps=40, horizon=8, stride=2,
                                  mean=mean, std=std)
     val = learned.build_dataset((256,), [4100, 4101], steps=40, horizon=8, stride=4,
                                 mean=mean, std=std)
@@ -103,6 +135,8 @@ def learned_gain(args) -> int:
     log(f"[learned] {data.x.shape[0]} training patches, positive cells {pos:.3f}, "
         f"pos_weight {pos_weight:.1f} ({time.perf_counter() - t0:.1f} s)")
     cfg = workloads.config(args.learned_config)
+    if args.learned_capacity:
+        cfg = cfg.replace(max_patches=args.learned_capacity)
     n = cfg.patch_cells[-1]
     # the predictor lives on the evaluation hierarchy of the learned policy
     h_bl = amr.Hierarchy(cfg)
@@ -119,8 +153,12 @@ def learned_gain(args) -> int:
 
     results = {}
     steps = args.steps
+    # B2: plain every 2 steps; B8: plain every 8 (the interval of the learned
+    # policy, same dilation); B8w: plain every 8 with a wider dilation; BL:
+    # learned every 8.  All run under the judge with fallback.
     for name, every, buffer, policy in (("B2", 2, cfg.tag_buffer, "plain"),
-                                         ("B8", 8, 3, "plain"),
+                                         ("B8", 8, cfg.tag_buffer, "plain"),
+                                         ("B8w", 8, 3, "plain"),
                                          ("BL", 8, cfg.tag_buffer, "learned")):
         if policy == "learned":
             h = h_bl
@@ -128,14 +166,7 @@ def learned_gain(args) -> int:
             h = amr.Hierarchy(cfg.replace(tag_buffer=buffer))
             amr.init_from_ic(h, workloads.initial_data(cfg, args.seed_eval))
         st = learned.run_policy(h, steps, every, policy, pred if policy == "learned" else None,
-                                tau, judge=(policy == "learned"))
-        if policy != "learned":
-            # coverage of the plain policies, measured on a replay (not timed)
-            h2 = amr.Hierarchy(cfg.replace(tag_buffer=buffer))
-            amr.init_from_ic(h2, workloads.initial_data(cfg, args.seed_eval))
-            cov = learned.run_policy(h2, steps, every, policy, judge=True)
-            st.uncovered_steps = cov.uncovered_steps
-            h2.close()
+                                tau, judge=True)
         results[name] = st.as_dict()
         log(f"[learned] {name}: {results[name]}")
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
@@ -146,7 +177,8 @@ def learned_gain(args) -> int:
                         "tau": tau, "validation": met},
            "policies": results,
            "gain_BL_vs_B2": results["B2"]["wall_per_tsim"] / results["BL"]["wall_per_tsim"],
-           "gain_BL_vs_B8": results["B8"]["wall_per_tsim"] / results["BL"]["wall_per_tsim"]}
+           "gain_BL_vs_B8": results["B8"]["wall_per_tsim"] / results["BL"]["wall_per_tsim"],
+           "gain_BL_vs_B8w": results["B8w"]["wall_per_tsim"] / results["BL"]["wall_per_tsim"]}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -162,12 +194,16 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="use this stage-kernel tile variant instead of autotuning")
     ap.add_argument("--learned", action="store_true",
                     help="train the refinement predictor and compare regrid policies")
     ap.add_argument("--learned-config", default="c4")
     ap.add_argument("--seed-eval", type=int, default=4100)
     ap.add_argument("--train-runs", type=int, default=8)
-    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--learned-capacity", type=int, default=0,
+                    help="patch capacity of the learned-comparison hierarchies (0: the config's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales HBM counters)")
     args = ap.parse_args()
@@ -191,10 +227,16 @@ def main() -> int:
     log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
         f"{h.leaf_cells()} leaf cells")
     tile = None
-    if mode == amr.EXEC_BATCHED and not args.no_autotune:
+    if args.tile is not None:
+        h.set_tile_variant(args.tile)
+        tile = h.tile_variant()
+        log(f"[bench] tile variant {tile}")
+    elif mode == amr.EXEC_BATCHED and not args.no_autotune:
         best, best_ms = h.autotune(5)
         tile = h.tile_variant()
         log(f"[bench] autotuned tile variant {tile} ({best_ms * 1e3:.1f} us per RHS launch)")
+    else:
+        tile = h.tile_variant()
 
     nstep = 0
 
@@ -228,7 +270,9 @@ def main() -> int:
     torch.cuda.synchronize()
     ms, launches, kcells = h.profile_read()
     h.profile(False)
-    log(f"[bench] stage kernel: {launches} launches over {psteps} steps, {ms:.2f} ms")
+    cells_per_launch = kcells / max(1, launches)
+    log(f"[bench] stage kernel: {launches} launches over {psteps} steps, {ms:.2f} ms, "
+        f"{cells_per_launch:.0f} leaf cells per launch")
     if h.check() != 0:
         log("[bench] WARNING: non-physical cells after the run")
     d = cfg.dim
@@ -272,9 +316,10 @@ def main() -> int:
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(None if tile is None else tile[0], cells_per_launch),
             "launches": launches,
             "avg_launch_ms": ms / max(1, launches),
+            "cells_per_launch": cells_per_launch,
             "flops_per_cell_update": f_step,
         },
         "roofline_hbm": {

@@ -336,12 +336,25 @@ class OracleAMR:
         return dt
 
     # --------------------------------------------------------------- tagging
+    def coarsening_candidates(self):
+        """Patches whose children are all leaves (the only ones a coarsening
+        request can name)."""
+        f = self.forest
+        return [k for k in f.keys()
+                if f.children[k] and all(f.is_leaf(c) for c in f.children[k])]
+
+    def tag_keys(self):
+        """Patches the tagger evaluates: every leaf, and every coarsening
+        candidate on its restricted data."""
+        return list(self.forest.leaves()) + self.coarsening_candidates()
+
     def tag(self, buf: int = 0):
-        """Per-leaf tag flag and per-cell dilated tags (ghosts of leaves filled)."""
+        """Tag flag of every patch of ``tag_keys()`` and per-cell dilated tags
+        (ghosts of those patches filled)."""
         cfg, d, ng = self.cfg, self.d, self.ng
         b = cfg.tag_buffer
         has, cells = {}, {}
-        for key in self.forest.leaves():
+        for key in self.tag_keys():
             a = self.U[buf][key]
             n = cfg.patch_cells[key[0]]
             rho, _, p, _ = euler.primitives(a, d, cfg.gamma)
@@ -365,13 +378,15 @@ class OracleAMR:
         return has, cells
 
     def requests(self, has):
+        """Refinement requests on tagged leaves below the finest level;
+        coarsening requests on candidates whose children are all untagged and
+        whose own restricted data are untagged too (without the last
+        condition a feature that the tagger sees on a coarse level but not
+        on the finer one would be refined and coarsened in turn)."""
         L = self.cfg.max_levels
         refine = [k for k in self.forest.leaves() if k[0] < L - 1 and has[k]]
-        coarsen = []
-        for k in self.forest.keys():
-            kids = self.forest.children[k]
-            if kids and all(self.forest.is_leaf(c) for c in kids) and not any(has[c] for c in kids):
-                coarsen.append(k)
+        coarsen = [k for k in self.coarsening_candidates()
+                   if not has[k] and not any(has[c] for c in self.forest.children[k])]
         return refine, coarsen
 
     def regrid(self, refine, coarsen, gen=None):
@@ -405,7 +420,7 @@ class OracleAMR:
     def adapt(self, flags=None):
         """Fill, tag, request and regrid; ``flags`` = (refine, coarsen) keys
         replaces this side's own requests (lockstep with another solver)."""
-        self.fill_ghosts(0, self.forest.leaves())
+        self.fill_ghosts(0, self.tag_keys())
         has, _ = self.tag(0)
         refine, coarsen = self.requests(has) if flags is None else flags
         return self.regrid(refine, coarsen)
@@ -417,7 +432,7 @@ class OracleAMR:
             self.set_initial(k, gen)
         history = []
         for _ in range(self.cfg.max_levels - 1):
-            self.fill_ghosts(0, self.forest.leaves())
+            self.fill_ghosts(0, self.tag_keys())
             has, _ = self.tag(0)
             refine, _ = self.requests(has)
             if not refine:

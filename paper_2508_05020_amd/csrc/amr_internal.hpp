@@ -16,6 +16,9 @@ constexpr int kNG = AMR_GHOST;   // ghost layers (flux-form Eq. (9) + WENO5 need
 constexpr int kMaxLev = AMR_MAX_LEVELS;
 
 // Per-level constants, mirrored on the device by value.
+// XCDs of the MI355X (gfx950): 8 dies of 32 compute units, one L2 each.
+constexpr int kXcds = 8;
+
 struct LevelC {
   int n;             // patch edge (cells)
   int full;          // n + 2 ng
@@ -62,15 +65,20 @@ struct Kernels {
   // (the prolonged ones)
   static void fill(const DevMesh& m, double* U, const int* list, int count, int* err,
                    bool coarse_only, hipStream_t s);
+  // prolonged ghost cells only, over (pid, ghost region) pairs
+  static void fill_cf(const DevMesh& m, double* U, const int* list, int count, int* err,
+                      hipStream_t s);
   // fuse = halo nodes outside the patch with a same-level source are read
   // from that source by the kernel itself; the others (prolonged) come from
-  // ghost layers filled by a coarse-only fill pass
+  // ghost layers filled before by fill_cf
   // lam_next (nullable, stage 3 only): accumulate the next step's CFL rate
   // over leaf cells not on coarse/fine faces (cfmask: per-pid face bits)
+  // ev0/ev1 (optional): events stamped at the dispatch's own start and end
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count,
                     const double* dt, bool fuse, unsigned long long* lam_next,
-                    const uint8_t* cfmask, hipStream_t s);
+                    const uint8_t* cfmask, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
   static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
                      const int* list, int count, const double* dt, double w,
                      unsigned long long* lam_next, hipStream_t s);

@@ -93,7 +93,7 @@ struct amr_hierarchy {
 
   // host mirrors of the work lists
   std::vector<int> lists;
-  amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfleaves{};
+  amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfregions{}, cands{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
   std::vector<int> last_created;
   std::vector<uint8_t> h_active_leaf;
@@ -104,7 +104,9 @@ struct amr_hierarchy {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<long long> ev_cells;
-  void prof_begin(hipEvent_t* a) {
+  // A pair of events for one profiled launch; the launch stamps them itself
+  // at its start and end, so the interval is the kernel's own duration.
+  void prof_pair(hipEvent_t* a, hipEvent_t* b, long long cells) {
     if (ev_used + 2 > ev_pool.size()) {
       for (int i = 0; i < 256; ++i) {
         hipEvent_t e;
@@ -113,11 +115,7 @@ struct amr_hierarchy {
       }
     }
     *a = ev_pool[ev_used++];
-    HIP_OK(hipEventRecord(*a, stream));
-  }
-  void prof_end(long long cells) {
-    hipEvent_t b = ev_pool[ev_used++];
-    HIP_OK(hipEventRecord(b, stream));
+    *b = ev_pool[ev_used++];
     ev_cells.push_back(cells);
   }
 
@@ -295,20 +293,36 @@ void sync_tables(amr_hierarchy* h, bool full) {
   const int a1 = begin_list();
   for (int pid : order)
     if (f.is_leaf(pid)) L.push_back(pid);
+  // (leaf, ghost region) pairs whose ghost cells have no same-level source:
+  // the region's neighbour offset, with components that leave the domain
+  // through a non-periodic boundary set to 0 (those ghosts copy the nearest
+  // interior cell), points at a missing same-level patch
   const int c0 = begin_list();
   for (int pid : order) {
     if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
     const int l = f.level[pid];
     const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
-    bool missing = false;
     for (const auto& off : f.moore()) {
-      int q[3];
-      if (f.shifted(l, c, off.data(), q) && f.lookup(l, q) < 0) {
-        missing = true;
-        break;
+      int src[3] = {off[0], off[1], off[2]};
+      bool self = true;
+      for (int j = 0; j < f.dim; ++j) {
+        const int v = c[j] + src[j];
+        if ((v < 0 || v >= f.np[l]) && !f.periodic[j]) src[j] = 0;
+        self &= src[j] == 0;
       }
+      int q[3];
+      if (self || !f.shifted(l, c, src, q) || f.lookup(l, q) >= 0) continue;
+      L.push_back(pid);
+      L.push_back((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
     }
-    if (missing) L.push_back(pid);
+  }
+  // coarsening candidates: patches whose children are all leaves
+  const int k0 = begin_list();
+  for (int pid : order) {
+    if (f.is_leaf(pid)) continue;
+    bool all_leaves = true;
+    for (int k = 0; k < f.nchild[pid]; ++k) all_leaves &= f.is_leaf(f.child[(size_t)pid * f.maxc + k]);
+    if (all_leaves) L.push_back(pid);
   }
   const int t0 = begin_list();
   h->leaf_cells = 0;
@@ -372,7 +386,8 @@ void sync_tables(amr_hierarchy* h, bool full) {
                           h->stream));
   h->all = {h->d_lists + a0, a1 - a0};
   h->leaves = {h->d_lists + a1, c0 - a1};
-  h->cfleaves = {h->d_lists + c0, t0 - c0};
+  h->cfregions = {h->d_lists + c0, (k0 - c0) / 2};
+  h->cands = {h->d_lists + k0, t0 - k0};
   h->tiles = {h->d_lists + t0, (r0 - t0) / 2};
   h->reflux = {h->d_lists + r0, nref};
   for (int l = 0; l < f.nlev; ++l) {
@@ -410,10 +425,15 @@ void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_onl
 }
 
 // ghosts the stage kernel reads from memory: all of them, or with the fused
-// halo only the prolonged ones (leaves with a missing same-level neighbour)
+// halo only the prolonged ones
 void stage_fill(amr_hierarchy* h, int buf) {
-  if (h->fuse_halo) do_fill(h, buf, h->cfleaves, true);
-  else do_fill(h, buf, h->leaves);
+  if (h->fuse_halo) {
+    over_list(h, h->cfregions, 2, [&](const int* p, int c) {
+      Kernels::fill_cf(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+    });
+  } else {
+    do_fill(h, buf, h->leaves);
+  }
 }
 
 void do_restrict(amr_hierarchy* h, int buf) {
@@ -433,11 +453,10 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
   const Kernels::TileVariant tv = Kernels::variant(h->dm.tile);
   const int tcells = tv.tx * tv.ty * tv.tz;
   over_list(h, h->tiles, 2, [&](const int* p, int c) {
-    hipEvent_t a{};
-    if (h->profiling) h->prof_begin(&a);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (h->profiling) h->prof_pair(&a, &b, (long long)c * tcells);
     Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
-                   stage == 3 ? lam_next : nullptr, h->d_cfmask, h->stream);
-    if (h->profiling) h->prof_end((long long)c * tcells);
+                   stage == 3 ? lam_next : nullptr, h->d_cfmask, h->stream, a, b);
   });
   over_list(h, h->reflux, 2, [&](const int* p, int c) {
     Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage],
@@ -471,10 +490,16 @@ void do_step(amr_hierarchy* h, double* dt, int cur) {
   do_stage(h, 3, dt, h->d_lam + (1 - cur));
 }
 
+// Tags of every leaf and of every coarsening candidate (on its restricted
+// data), then the requests.
 void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_t* cells) {
   do_fill(h, buf, h->leaves);
+  do_fill(h, buf, h->cands);
   over_list(h, h->leaves, 1, [&](const int* p, int c) {
     Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, cells ? h->d_raw : nullptr, h->stream);
+  });
+  over_list(h, h->cands, 1, [&](const int* p, int c) {
+    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, nullptr, h->stream);
   });
   if (cells)
     over_list(h, h->leaves, 1, [&](const int* p, int c) {
@@ -609,7 +634,11 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
       for (int l = 0; l < f.nlev; ++l) t += (long long)f.cap[l] * Kernels::tiles_per_patch(v, f.n[l]);
       tiles = std::max(tiles, t);
     }
-    h->lists_cap = 2 * tiles + 9 * mp + 64;
+    // all, leaves, coarsening candidates, reflux (2), restriction, new
+    // patches: 7 per patch; ghost regions: 2 per region and patch; tiles: 2
+    // per tile
+    const long long regions = ipow(3, cfg->dim) - 1;
+    h->lists_cap = 2 * tiles + (7 + 2 * regions) * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);

@@ -14,6 +14,7 @@
 // of the definitions they implement (no fma), so that integer decisions (tags,
 // positivity switches) are taken on the same values as the FP64 reference.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -103,6 +104,7 @@ template <int D>
 __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int lf,
                              const int g[3], double out[D + 2]) {
   constexpr int NV = D + 2;
+  constexpr int NS = 2 * D + 1;  // coarse stencil: centre, then (+1, -1) per direction
   const int lc = lf - 1;
   const LevelC& C = m.lv[lc];
   int gc[3] = {0, 0, 0};
@@ -111,24 +113,47 @@ __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int
     gc[j] = g[j] >> 1;
     sig[j] = (g[j] & 1) ? 1.0 : -1.0;
   }
-  double phi[NV];
-  if (!fetch_cell<D>(m, U, lc, gc, phi)) return false;
-  double s[D][NV];
+  // all map lookups first, then all loads, so the latencies overlap
+  int pids[NS];
+  long long offs[NS];
+  const long long vs = var_stride<D>(C.full);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    int gs[3] = {gc[0], gc[1], gc[2]};
+    if (s > 0) {
+      const int j = (s - 1) >> 1;
+      gs[j] = bc_map(gc[j] + (((s - 1) & 1) ? -1 : 1), C.cells, m.periodic[j]);
+    }
+    int q[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) {
+      q[j] = gs[j] / C.n;
+      c[j] = gs[j] - q[j] * C.n;
+    }
+    pids[s] = map_at<D>(m, lc, q);
+    offs[s] = box_off<D>(C.full, c[0] + NG, c[1] + NG, c[2] + NG);
+  }
+  bool found = true;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) found &= pids[s] >= 0;
+  if (!found) return false;
+  double val[NS][NV];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double* P = U + patch_base(m, pids[s], lc) + offs[s];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) val[s][v] = P[v * vs];
+  }
+  const double* phi = val[0];
+  double sl[D][NV];
+#pragma unroll
   for (int j = 0; j < D; ++j) {
-    int gp[3] = {gc[0], gc[1], gc[2]};
-    int gm[3] = {gc[0], gc[1], gc[2]};
-    gp[j] = bc_map(gc[j] + 1, C.cells, m.periodic[j]);
-    gm[j] = bc_map(gc[j] - 1, C.cells, m.periodic[j]);
-    double up[NV], dn[NV];
-    if (!fetch_cell<D>(m, U, lc, gp, up)) return false;
-    if (!fetch_cell<D>(m, U, lc, gm, dn)) return false;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double a = up[v] - phi[v];
-      const double b = phi[v] - dn[v];
+      const double a = val[1 + 2 * j][v] - phi[v];
+      const double b = phi[v] - val[2 + 2 * j][v];
       const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
       const double mag = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
-      s[j][v] = same ? copysign(mag, a) : 0.0;
+      sl[j][v] = same ? copysign(mag, a) : 0.0;
     }
   }
   bool bad = false;
@@ -137,7 +162,7 @@ __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double x = phi[v];
-      for (int j = 0; j < D; ++j) x = x + (((c >> j) & 1) ? 0.25 : -0.25) * s[j][v];
+      for (int j = 0; j < D; ++j) x = x + (((c >> j) & 1) ? 0.25 : -0.25) * sl[j][v];
       ch[v] = x;
     }
     const double p = pressure_exact<D>(ch, m.gm1);
@@ -146,7 +171,7 @@ __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double x = phi[v];
-    for (int j = 0; j < D; ++j) x = x + (sig[j] * 0.25) * (bad ? 0.0 : s[j][v]);
+    for (int j = 0; j < D; ++j) x = x + (sig[j] * 0.25) * (bad ? 0.0 : sl[j][v]);
     out[v] = x;
   }
   return true;
@@ -236,14 +261,66 @@ __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
   }
 }
 
+// Ghost cells without a same-level source: one work item per (leaf, ghost
+// region), region = neighbour offset r in {-1,0,1}^D coded as
+// (r0+1) + 3 (r1+1) + 9 (r2+1); the host lists only regions whose source
+// position (after the physical-boundary clamp) holds no same-level patch, so
+// every cell of the region is prolonged from level l-1.
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m, double* __restrict__ U,
+                                                const int* __restrict__ list, int count,
+                                                int* __restrict__ err) {
+  constexpr int NV = D + 2;
+  if ((int)blockIdx.x >= count) return;
+  const int pid = list[2 * blockIdx.x];
+  const int code = list[2 * blockIdx.x + 1];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, full = L.full;
+  const long long vs = var_stride<D>(full);
+  double* P = U + patch_base(m, pid, l);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  int start[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+  int total = 1;
+  for (int j = 0; j < D; ++j) {
+    const int r = (j == 0 ? code : (j == 1 ? code / 3 : code / 9)) % 3 - 1;
+    start[j] = r < 0 ? -NG : (r == 0 ? 0 : n);
+    ext[j] = r == 0 ? n : NG;
+    total *= ext[j];
+  }
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    int c[3] = {start[0] + idx % ext[0], 0, 0};
+    if constexpr (D >= 2) c[1] = start[1] + (idx / ext[0]) % ext[1];
+    if constexpr (D >= 3) c[2] = start[2] + idx / (ext[0] * ext[1]);
+    int g[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c[j], L.cells, m.periodic[j]);
+    double val[NV];
+    const bool ok = (l > 0) && prolong_cell<D>(m, U, l, g, val);
+    if (!ok) {
+      err[0] = 1;
+      for (int v = 0; v < NV; ++v) val[v] = __builtin_nan("");
+    }
+    const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[v * vs + off] = val[v];
+  }
+}
+
+// Work item of this block when the grid is a whole number of groups of kXcds
+// blocks.  Workgroups are dealt to the chip's XCDs in turn (block b runs on
+// XCD b mod kXcds), and each XCD has its own L2; the mapping gives every XCD
+// one contiguous run of the work list, so tiles of one patch and of
+// neighbouring patches (the list is in level, z, y, x order), which read
+// each other's cells as halos, share an L2.
+__device__ __forceinline__ int xcd_item(int count) {
+  const int per_xcd = (int)gridDim.x / kXcds;
+  return ((int)blockIdx.x % kXcds) * per_xcd + (int)blockIdx.x / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // fused right-hand side + SSP-RK3 stage on (pid, tile) work items
 // ---------------------------------------------------------------------------
 
-// WENO5-JS value at the edge between c and d (five nodes a..e).  The
-// nonlinear weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
-// t_k = (eps + beta_k)^2, are evaluated as cross products so that one
-// division serves all three weights.
 // 1/x from the hardware reciprocal estimate refined by two Newton steps
 // (relative error near one ulp); used where correct rounding is not required.
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -254,25 +331,56 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e,
-                                        double eps) {
-  const double q0 = fma(15.0, c, fma(-10.0, b, 3.0 * a)) * 0.125;
-  const double q1 = fma(3.0, d, fma(6.0, c, -b)) * 0.125;
-  const double q2 = fma(6.0, d, fma(3.0, c, -e)) * 0.125;
-  const double k0 = fma(-2.0, b, a) + c, s0 = fma(3.0, c, fma(-4.0, b, a));
-  const double k1 = fma(-2.0, c, b) + d, s1 = b - d;
-  const double k2 = fma(-2.0, d, c) + e, s2 = fma(3.0, c, fma(-4.0, d, e));
-  const double c1312 = 13.0 / 12.0;
-  const double b0 = fma(c1312 * k0, k0, (0.25 * s0) * s0);
-  const double b1 = fma(c1312 * k1, k1, (0.25 * s1) * s1);
-  const double b2 = fma(c1312 * k2, k2, (0.25 * s2) * s2);
-  const double e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+// Nonlinear WENO5-JS combination of three candidates from their smoothness
+// indicators.  The weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
+// t_k = (eps + beta_k)^2 and d = (1, 10, 5)/16 are evaluated as cross
+// products, so one division serves all three.  Inputs are scaled: candidates
+// by 8, indicators and eps by 4; with power-of-two factors the scaling is
+// exact and only the final 1/8 is applied.
+__device__ __forceinline__ double weno_combine(double b0, double b1, double b2, double q0,
+                                               double q1, double q2, double eps4) {
+  const double e0 = eps4 + b0, e1 = eps4 + b1, e2 = eps4 + b2;
   const double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
-  const double a0 = (1.0 / 16.0) * (t1 * t2);
-  const double a1 = (10.0 / 16.0) * (t0 * t2);
-  const double a2 = (5.0 / 16.0) * (t0 * t1);
+  const double a0 = t1 * t2;
+  const double a1 = 10.0 * (t0 * t2);
+  const double a2 = 5.0 * (t0 * t1);
   const double num = fma(a2, q2, fma(a1, q1, a0 * q0));
-  return num * rcp_nr((a0 + a1) + a2);
+  return (num * rcp_nr((a0 + a1) + a2)) * 0.125;
+}
+
+// WENO5-JS point values on both sides of the edge between v2 and v3 from the
+// six nodes v0..v5: the left-biased value from v0..v4 and the right-biased
+// value from the mirrored stencil v5..v1.  Candidates: the quadratic through
+// three consecutive nodes evaluated at the edge (x8), two of which the sides
+// share; indicators (x4): 13/12 (second difference)^2 + 1/4 (first-difference
+// form)^2 of the Jiang-Shu definition, with the second differences of the
+// two middle windows shared.
+__device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
+                                           double v5, double eps4, double& L, double& R) {
+  const double qa = fma(15.0, v2, fma(-10.0, v1, 3.0 * v0));  // left, nodes v0..v2
+  const double qb = fma(3.0, v3, fma(6.0, v2, -v1));          // nodes v1..v3 (both sides)
+  const double qc = fma(6.0, v3, fma(3.0, v2, -v4));          // nodes v2..v4 (both sides)
+  const double qd = fma(15.0, v3, fma(-10.0, v4, 3.0 * v5));  // right, nodes v3..v5
+  const double k0 = fma(-2.0, v1, v0) + v2;
+  const double k1 = fma(-2.0, v2, v1) + v3;
+  const double k2 = fma(-2.0, v3, v2) + v4;
+  const double k3 = fma(-2.0, v4, v3) + v5;
+  constexpr double c4 = 4.0 * (13.0 / 12.0);
+  const double g0 = c4 * k0, g1 = c4 * k1, g2 = c4 * k2, g3 = c4 * k3;
+  const double sl0 = fma(3.0, v2, fma(-4.0, v1, v0));
+  const double sl1 = v1 - v3;
+  const double sl2 = fma(3.0, v2, fma(-4.0, v3, v4));
+  const double sr0 = fma(3.0, v3, fma(-4.0, v4, v5));
+  const double sr1 = v4 - v2;
+  const double sr2 = fma(3.0, v3, fma(-4.0, v2, v1));
+  const double bl0 = fma(g0, k0, sl0 * sl0);
+  const double bl1 = fma(g1, k1, sl1 * sl1);
+  const double bl2 = fma(g2, k2, sl2 * sl2);
+  const double br0 = fma(g3, k3, sr0 * sr0);
+  const double br1 = fma(g2, k2, sr1 * sr1);
+  const double br2 = fma(g1, k1, sr2 * sr2);
+  L = weno_combine(bl0, bl1, bl2, qa, qb, qc, eps4);
+  R = weno_combine(br0, br1, br2, qd, qc, qb, eps4);
 }
 
 __device__ __forceinline__ double central4(double b, double c, double d, double e) {
@@ -439,6 +547,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     else base = a1 * E0 + (a0 + 4);
     EdgeState<D> wl, wr;
     double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
+    const double eps4 = 4.0 * m.eps;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const double* col = sP + q * NEXT + base;
@@ -448,8 +557,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
         lv[q] = central4(v1, v2, v3, v4);
         rv[q] = lv[q];
       } else {
-        lv[q] = weno5(v0, v1, v2, v3, v4, m.eps);
-        rv[q] = weno5(v5, v4, v3, v2, v1, m.eps);
+        weno5_pair(v0, v1, v2, v3, v4, v5, eps4, lv[q], rv[q]);
       }
       lo[q] = v2;
       hi[q] = v3;
@@ -469,13 +577,14 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     edge_flux<D, J>(m, wr, UR, FR, sr);
     const double S = fmax(sr, sl);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v * NED + e] = 0.5 * fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
+    for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
   }
   __syncthreads();
 
   // 3. face fluxes G (flux form of Eq. (9)) and their divergence
   const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
   constexpr double c24 = 1.0 / 24.0;
+  const double half_inv_h = 0.5 * inv_h;
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int cell = tid + cc * NT;
@@ -501,13 +610,15 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
+      // edge fluxes are stored doubled (the Rusanov 1/2 is applied here, as
+      // 1/2 inv_h, and to the boundary faces; power-of-two scaling is exact)
       const double* F = sF + v * NED + eb;
       const double Fm2 = F[0], Fm1 = F[ESTEP], F0 = F[2 * ESTEP], Fp1 = F[3 * ESTEP];
       const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
       const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
-      acc[cc][v] = fma(-(Gp - Gm), inv_h, acc[cc][v]);
-      if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = Gm;
-      if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = Gp;
+      acc[cc][v] = fma(-(Gp - Gm), half_inv_h, acc[cc][v]);
+      if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = 0.5 * Gm;
+      if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
     }
   }
   __syncthreads();
@@ -528,9 +639,10 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
   constexpr int NU = (S::T0 + 8) * (D >= 2 ? S::T1 + 8 : 1);
   __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
   __shared__ double sF[(D + 2) * S::EDMAX];
-  if ((int)blockIdx.x >= count) return;
-  const int pid = tiles[2 * blockIdx.x];
-  const int tix = tiles[2 * blockIdx.x + 1];
+  const int item = xcd_item(count);
+  if (item >= count) return;
+  const int pid = tiles[2 * item];
+  const int tix = tiles[2 * item + 1];
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n, full = L.full;
@@ -897,7 +1009,9 @@ __global__ void k_requests(DevMesh m, const uint8_t* __restrict__ has_tag,
   if (al == 1) {
     rq = (has_tag[pid] && m.level[pid] < m.nlev - 1) ? 1 : 0;
   } else if (al == 2) {
-    cq = 1;
+    // a coarsening candidate (all children leaves) was tagged on its own
+    // restricted data as well; it is coarsened only if that is untagged too
+    cq = has_tag[pid] ? 0 : 1;
     const int nc = m.nchild[pid];
     for (int k = 0; k < nc; ++k) {
       const int c = m.child[(long long)pid * m.maxc + k];
@@ -1000,6 +1114,16 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
     else hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__);             \
   } while (0)
 
+void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, int* err,
+                      hipStream_t s) {
+  if (count <= 0) return;
+  switch (m.dim) {
+    case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
+    case 2: k_fill_cf<2, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
+    default: k_fill_cf<3, 256><<<count, 256, 0, s>>>(m, U, list, count, err); break;
+  }
+}
+
 void Kernels::fill(const DevMesh& m, double* U, const int* list, int count, int* err,
                    bool coarse_only, hipStream_t s) {
   if (count <= 0) return;
@@ -1047,16 +1171,27 @@ int Kernels::tiles_per_patch(int v, int n) {
 void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count, const double* dt,
                     bool fuse, unsigned long long* lam_next, const uint8_t* cfmask,
-                    hipStream_t s) {
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (count <= 0) return;
-#define AMR_STAGE(D, TX, TY, TZ, NT)                                                        \
+  // one block per work item, rounded up to whole groups of kXcds blocks (see
+  // xcd_item)
+  const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
+#define AMR_STAGE_F(D, TX, TY, TZ, NT, F)                                                   \
   do {                                                                                      \
-    if (fuse)                                                                               \
-      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, true>), dim3(count), dim3(NT), 0, s, m, \
-                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);       \
+    if (ev0)                                                                                \
+      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, ev0,  \
+                            ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,  \
+                            cfmask);                                                        \
     else                                                                                    \
-      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, false>), dim3(count), dim3(NT), 0, s, m,\
-                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);       \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, m, mode, \
+                         Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);             \
+  } while (0)
+#define AMR_STAGE(D, TX, TY, TZ, NT)        \
+  do {                                      \
+    if (fuse)                               \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, true); \
+    else                                    \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, false);\
   } while (0)
   switch (m.tile) {
     case 0: AMR_STAGE(1, 16, 1, 1, 64); break;
@@ -1069,6 +1204,7 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
     default: AMR_STAGE(3, 4, 4, 4, 128); break;
   }
 #undef AMR_STAGE
+#undef AMR_STAGE_F
 }
 
 void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,

@@ -12,9 +12,12 @@ network sees features at the cell sizes of several AMR levels.
 Policies (wall-clock per unit simulated time is the figure of merit):
   plain  -- gradient tagging + regrid every ``every`` steps;
   learned -- every ``every`` steps regrid with refine = plain | predicted and
-             coarsen = plain & predicted; at every step the plain tagger judges
-             the mesh and an immediate plain regrid follows when any tag is
-             uncovered (the fallback).
+             coarsen = plain & predicted.
+With the judge on, after every step the plain tagger checks that every tagged
+cell lies in a leaf of the finest level allowed, and an immediate plain regrid
+follows when one does not (the fallback).  Every policy run under the judge
+therefore advances on meshes that cover the plain tags at the same rate, and
+the policies differ only in how many regrids and fallbacks that costs.
 """
 from __future__ import annotations
 
@@ -218,9 +221,8 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
             unc = h.judge()
             if unc:
                 uncovered += 1
-                if policy == "learned":
-                    h.adapt()
-                    fallbacks += 1
+                h.adapt()
+                fallbacks += 1
         if every > 0 and s % every == 0:
             regrids += 1
             if policy == "plain":

@@ -95,7 +95,7 @@ def test_rk_stages_parity(name, amr):
 def test_tag_and_requests_exact(name, amr):
     o, h, pid_of, key_of = _pair(name, amr)
     refine, coarsen, cells = h.tag(0, cell_tags=True)
-    o.fill_ghosts(0, o.forest.leaves())
+    o.fill_ghosts(0, o.tag_keys())
     has, ocells = o.tag(0)
     oref, ocoa = o.requests(has)
     r = refine.cpu().numpy()
@@ -114,7 +114,7 @@ def test_tag_and_requests_exact(name, amr):
 @pytest.mark.parametrize("name", CASES)
 def test_regrid_parity(name, amr):
     o, h, pid_of, key_of = _pair(name, amr)
-    o.fill_ghosts(0, o.forest.leaves())
+    o.fill_ghosts(0, o.tag_keys())
     has, _ = o.tag(0)
     oref, ocoa = o.requests(has)
     # add coarsening requests on every non-leaf so that the coarsening rule is
@@ -151,7 +151,7 @@ def test_lockstep_steps_with_regrid(name, amr):
         o.step()
         if s % 2 == 0:
             refine, coarsen, _ = h.tag(0)
-            o.fill_ghosts(0, o.forest.leaves())
+            o.fill_ghosts(0, o.tag_keys())
             has, _ = o.tag(0)
             oref, ocoa = o.requests(has)
             r = {key_of[p] for p in np.nonzero(refine.cpu().numpy())[0]}

@@ -73,6 +73,12 @@ def _conservation_error(cls, d, steps=4):
         gen = W.blasts(3001, dim=3)
     o.init_from_ic(gen)
     assert o.forest.levels() == 3
+    # coarsen a random third of the finest families so that coarse/fine faces
+    # exist whatever the tagger refined
+    rnd = random.Random(7)
+    cand = [k for k in o.coarsening_candidates() if k[0] == cfg.max_levels - 2]
+    o.regrid([], rnd.sample(cand, max(1, len(cand) // 3)))
+    assert o.forest.levels() == 3
     t0 = o.totals()
     scale = []
     for v in range(cfg.nvar):
@@ -370,3 +376,37 @@ def test_dt_bruteforce():
             c = math.sqrt(1.4 * p / r)
             lam = max(lam, (abs(ux) + c + abs(uy) + c) / h)
     assert o.compute_dt(0) == pytest.approx(o.cfg.cfl / lam, rel=1e-12)
+
+
+def _density_ramp(slope):
+    def f(pts):
+        rho = 1.0 + slope * pts[0]
+        zero = np.zeros_like(rho)
+        return rho, [zero, zero], np.ones_like(rho)
+    return f
+
+
+@pytest.mark.parametrize("fine_rel,expect_coarsen", [(0.75, False), (0.3, True)])
+def test_coarsening_needs_untagged_parent(fine_rel, expect_coarsen):
+    """A density ramp whose centred relative difference is at most
+    fine_rel * theta on the fine level (never tagged there) and twice that on
+    the coarse level.  The refined family is coarsened only when the parent's
+    own restricted data are untagged as well; at 0.75 the parent is tagged
+    near rho = 1 and keeps its children."""
+    cfg = _cfg(2, 32, (16, 16), periodic=False, ic="density_wave")
+    theta = cfg.tag_theta
+    h_fine = 1.0 / 64.0
+    gen = _density_ramp(fine_rel * theta / h_fine)
+    o = OracleAMR(cfg)
+    for k in o.forest.keys():
+        o.set_initial(k, gen)
+    parent = (0, (0, 0))
+    o.regrid([parent], [], gen)
+    o.restrict(0)
+    o.fill_ghosts(0, o.tag_keys())
+    has, _ = o.tag(0)
+    kids = o.forest.children[parent]
+    assert len(kids) == 4 and not any(has[c] for c in kids)
+    assert has[parent] == (not expect_coarsen)
+    _, coarsen = o.requests(has)
+    assert (parent in coarsen) == expect_coarsen
