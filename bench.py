@@ -49,7 +49,9 @@ def log(msg: str):
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 COUNTERS = os.path.join(ROOT, "profiles", "k_stage_counters.json")
-KERNEL_SOURCES = ("paper_2508_05020_amd/csrc/kernels.hip", "paper_2508_05020_amd/csrc/amr_internal.hpp")
+# sources the stage kernel is compiled from
+KERNEL_SOURCES = ("paper_2508_05020_amd/csrc/stage.hip", "paper_2508_05020_amd/csrc/device_common.hpp",
+                  "paper_2508_05020_amd/csrc/amr_internal.hpp")
 
 
 def kernel_source_hash() -> str:

@@ -35,6 +35,9 @@ STATUS = {0: "AMR_OK", -1: "AMR_E_ARG", -2: "AMR_E_CAPACITY", -3: "AMR_E_HIP",
           -4: "AMR_E_MESH", -5: "AMR_E_NONPHYSICAL", -6: "AMR_E_STATE"}
 
 
+E_CAPACITY = -2
+
+
 class AMRError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")

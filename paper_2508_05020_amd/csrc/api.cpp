@@ -530,6 +530,13 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
     h->err = e.what();
     return AMR_E_CAPACITY;
   }
+  if (created.empty() && deleted.empty()) {
+    // mesh unchanged: tables, step graphs and the CFL rate stay valid
+    h->last_created.clear();
+    if (ncreated) *ncreated = 0;
+    if (ndeleted) *ndeleted = 0;
+    return AMR_OK;
+  }
   const std::string why = h->forest.validate();
   if (!why.empty()) {
     h->err = why;

@@ -1,0 +1,504 @@
+// The fused stage kernel of libamr for gfx950 (CDNA4, wave64): per (patch,
+// tile) work item, primitives of the tile and its halos in LDS, WENO5-JS
+// interpolation and the Rusanov flux at every edge (Eq. (10)-(12)), the
+// face fluxes and divergence of Eq. (9) in flux form, and the SSP-RK3 stage
+// combination; also the tile variants the autotuner chooses from.
+//
+// Floating-point contract: implicit contraction is off and every fused
+// multiply-add is written with fma(), so a cell's operation sequence is fixed
+// by this source and identical for every tile variant, fused or explicit
+// halo, per-patch or batched launch.
+#include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "amr_internal.hpp"
+
+// no implicit contraction anywhere in this file
+#pragma clang fp contract(off)
+
+#include "device_common.hpp"
+
+namespace amr {
+namespace {
+
+// ---------------------------------------------------------------------------
+// fused right-hand side + SSP-RK3 stage on (pid, tile) work items
+// ---------------------------------------------------------------------------
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (relative error near one ulp); used where correct rounding is not required.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Nonlinear WENO5-JS combination of three candidates from their smoothness
+// indicators.  The weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
+// t_k = (eps + beta_k)^2 and d = (1, 10, 5)/16 are evaluated as cross
+// products, so one division serves all three.  Inputs are scaled: candidates
+// by 8, indicators and eps by 4; with power-of-two factors the scaling is
+// exact and only the final 1/8 is applied.
+__device__ __forceinline__ double weno_combine(double b0, double b1, double b2, double q0,
+                                               double q1, double q2, double eps4) {
+  const double e0 = eps4 + b0, e1 = eps4 + b1, e2 = eps4 + b2;
+  const double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
+  const double a0 = t1 * t2;
+  const double a1 = 10.0 * (t0 * t2);
+  const double a2 = 5.0 * (t0 * t1);
+  const double num = fma(a2, q2, fma(a1, q1, a0 * q0));
+  return (num * rcp_nr((a0 + a1) + a2)) * 0.125;
+}
+
+// WENO5-JS point values on both sides of the edge between v2 and v3 from the
+// six nodes v0..v5: the left-biased value from v0..v4 and the right-biased
+// value from the mirrored stencil v5..v1.  Candidates: the quadratic through
+// three consecutive nodes evaluated at the edge (x8), two of which the sides
+// share; indicators (x4): 13/12 (second difference)^2 + 1/4 (first-difference
+// form)^2 of the Jiang-Shu definition, with the second differences of the
+// two middle windows shared.
+__device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
+                                           double v5, double eps4, double& L, double& R) {
+  const double qa = fma(15.0, v2, fma(-10.0, v1, 3.0 * v0));  // left, nodes v0..v2
+  const double qb = fma(3.0, v3, fma(6.0, v2, -v1));          // nodes v1..v3 (both sides)
+  const double qc = fma(6.0, v3, fma(3.0, v2, -v4));          // nodes v2..v4 (both sides)
+  const double qd = fma(15.0, v3, fma(-10.0, v4, 3.0 * v5));  // right, nodes v3..v5
+  const double k0 = fma(-2.0, v1, v0) + v2;
+  const double k1 = fma(-2.0, v2, v1) + v3;
+  const double k2 = fma(-2.0, v3, v2) + v4;
+  const double k3 = fma(-2.0, v4, v3) + v5;
+  constexpr double c4 = 4.0 * (13.0 / 12.0);
+  const double g0 = c4 * k0, g1 = c4 * k1, g2 = c4 * k2, g3 = c4 * k3;
+  const double sl0 = fma(3.0, v2, fma(-4.0, v1, v0));
+  const double sl1 = v1 - v3;
+  const double sl2 = fma(3.0, v2, fma(-4.0, v3, v4));
+  const double sr0 = fma(3.0, v3, fma(-4.0, v4, v5));
+  const double sr1 = v4 - v2;
+  const double sr2 = fma(3.0, v3, fma(-4.0, v2, v1));
+  const double bl0 = fma(g0, k0, sl0 * sl0);
+  const double bl1 = fma(g1, k1, sl1 * sl1);
+  const double bl2 = fma(g2, k2, sl2 * sl2);
+  const double br0 = fma(g3, k3, sr0 * sr0);
+  const double br1 = fma(g2, k2, sr1 * sr1);
+  const double br2 = fma(g1, k1, sr2 * sr2);
+  L = weno_combine(bl0, bl1, bl2, qa, qb, qc, eps4);
+  R = weno_combine(br0, br1, br2, qd, qc, qb, eps4);
+}
+
+__device__ __forceinline__ double central4(double b, double c, double d, double e) {
+  return fma(9.0, c + d, -(b + e)) * 0.0625;
+}
+
+template <int D>
+struct EdgeState {
+  double p, T, u[D];
+};
+
+// Conserved state and direction-J flux of an edge state (Eq. (1)-(3), (5)-(7)).
+template <int D, int J>
+__device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& w,
+                                          double U[D + 2], double F[D + 2], double& speed) {
+  const double rho = w.p * rcp_nr(w.T);
+  double uu = w.u[0] * w.u[0];
+#pragma unroll
+  for (int i = 1; i < D; ++i) uu = fma(w.u[i], w.u[i], uu);
+  const double E = fma(0.5 * rho, uu, w.p * m.igm1);
+  U[0] = rho;
+  F[0] = rho * w.u[J];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double mi = rho * w.u[i];
+    U[1 + i] = mi;
+    F[1 + i] = (i == J) ? fma(mi, w.u[J], w.p) : mi * w.u[J];
+  }
+  U[D + 1] = E;
+  F[D + 1] = (E + w.p) * w.u[J];
+  speed = sqrt(m.gamma * w.T) + fabs(w.u[J]);
+}
+
+template <int D, int TX, int TY, int TZ>
+struct TileShape {
+  static constexpr int T0 = TX;
+  static constexpr int T1 = D >= 2 ? TY : 1;
+  static constexpr int T2 = D >= 3 ? TZ : 1;
+  static constexpr int NCELL = T0 * T1 * T2;
+  static constexpr int ext(int j) {
+    return (T0 + (j == 0 ? 8 : 0)) * (T1 + (j == 1 ? 8 : 0)) * (T2 + (j == 2 ? 8 : 0));
+  }
+  static constexpr int edges(int j) {
+    return (T0 + (j == 0 ? 3 : 0)) * (T1 + (j == 1 ? 3 : 0)) * (T2 + (j == 2 ? 3 : 0));
+  }
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int EXTMAX = cmax(ext(0), cmax(D >= 2 ? ext(1) : 0, D >= 3 ? ext(2) : 0));
+  static constexpr int EDMAX =
+      cmax(edges(0), cmax(D >= 2 ? edges(1) : 0, D >= 3 ? edges(2) : 0));
+};
+
+// Primitives (p, T, u_j) of one node from its conserved values.
+template <int D>
+__device__ __forceinline__ void node_primitives(const DevMesh& m, const double* u, double* q) {
+  const double r = rcp_nr(u[0]);
+  double ke = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ui = u[1 + i] * r;
+    ke = (i == 0) ? u[1] * ui : fma(u[1 + i], ui, ke);
+    q[2 + i] = ui;
+  }
+  const double p = m.gm1 * fma(-0.5, ke, u[D + 1]);
+  q[0] = p;
+  q[1] = p * r;
+}
+
+// Conserved values of a node at patch-local cell c (may lie in the halo):
+// from the patch itself, or by the ghost-fill rule when outside the patch.
+template <int D, bool FUSE>
+__device__ __forceinline__ void node_conserved(const DevMesh& m, const double* __restrict__ Uin,
+                                               const double* __restrict__ Pin, int n, int full,
+                                               const int c[3], const int pc[3], int l,
+                                               double* u) {
+  constexpr int NV = D + 2;
+  bool inside = true;
+  for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
+  if (FUSE && !inside) {
+    int g[3] = {0, 0, 0};
+    for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c[j], m.lv[l].cells, m.periodic[j]);
+    if (fetch_cell<D>(m, Uin, l, g, u)) return;
+    // no same-level source: the prolonged ghost value was written into the
+    // patch's own ghost layer by the coarse-ghost fill pass
+  }
+  const long long vs = var_stride<D>(full);
+  const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+}
+
+// 1D/2D: primitives of the tile plus 4-node halos in every direction
+// (corner nodes, used by no stencil, are skipped), loaded once per launch.
+template <int D, int TX, int TY, int NT, bool FUSE>
+__device__ __forceinline__ void load_union(const DevMesh& m, const double* __restrict__ Uin,
+                                           const double* __restrict__ Pin, int n, int full,
+                                           const int o[3], const int pc[3], int l, double* sP) {
+  constexpr int T0 = TX, T1 = D >= 2 ? TY : 1;
+  constexpr int U0 = T0 + 8, U1 = D >= 2 ? T1 + 8 : 1;
+  constexpr int NU = U0 * U1;
+  constexpr int NQ = D + 2;
+  for (int idx = threadIdx.x; idx < NU; idx += NT) {
+    const int e0 = idx % U0, e1 = idx / U0;
+    const bool hx = e0 < 4 || e0 >= T0 + 4;
+    const bool hy = D >= 2 && (e1 < 4 || e1 >= T1 + 4);
+    if (hx && hy) continue;
+    const int c[3] = {o[0] + e0 - 4, D >= 2 ? o[1] + e1 - 4 : 0, 0};
+    double u[D + 2], q[NQ];
+    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
+    node_primitives<D>(m, u, q);
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) sP[k * NU + idx] = q[k];
+  }
+}
+
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool UNION>
+__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
+                                                const double* __restrict__ Pin,
+                                                double* __restrict__ frp, int n, int full,
+                                                const int o[3], const int pc[3], int l,
+                                                double* sP, double* sF,
+                                                double acc[][D + 2], double inv_h) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int NQ = D + 2;  // interpolated primitives: p, T, u_j
+  constexpr int E0 = UNION ? S::T0 + 8 : S::T0 + (J == 0 ? 8 : 0);
+  constexpr int E1 = UNION ? (D >= 2 ? S::T1 + 8 : 1) : S::T1 + (J == 1 ? 8 : 0);
+  constexpr int E2 = UNION ? 1 : S::T2 + (J == 2 ? 8 : 0);
+  constexpr int NEXT = E0 * E1 * E2;
+  constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
+  constexpr int G1 = S::T1 + (J == 1 ? 3 : 0);
+  constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
+  constexpr int NED = G0 * G1 * G2;
+  constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
+  constexpr int CPT = (S::NCELL + NT - 1) / NT;
+  const int tid = threadIdx.x;
+
+  // 1. primitives of the tile extended by 4 nodes on both sides along J
+  // (the union layout is loaded once by the caller for all directions)
+  if constexpr (!UNION) {
+    for (int idx = tid; idx < NEXT; idx += NT) {
+      const int e0 = idx % E0;
+      const int e1 = (idx / E0) % E1;
+      const int e2 = idx / (E0 * E1);
+      const int c[3] = {o[0] + e0 - (J == 0 ? 4 : 0), o[1] + e1 - (J == 1 ? 4 : 0),
+                        o[2] + e2 - (J == 2 ? 4 : 0)};
+      double u[NV], q[NQ];
+      node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
+      node_primitives<D>(m, u, q);
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) sP[k * NEXT + idx] = q[k];
+    }
+    __syncthreads();
+  }
+
+  // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
+  for (int e = tid; e < NED; e += NT) {
+    const int a0 = e % G0;
+    const int a1 = (e / G0) % G1;
+    const int a2 = e / (G0 * G1);
+    // layout index of node i-2 of this edge's window
+    int base;
+    if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);
+    else if constexpr (J == 0) base = (D >= 2 ? (a1 + 4) * E0 : 0) + a0;
+    else base = a1 * E0 + (a0 + 4);
+    EdgeState<D> wl, wr;
+    double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
+    const double eps4 = 4.0 * m.eps;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double* col = sP + q * NEXT + base;
+      const double v0 = col[0], v1 = col[STEP], v2 = col[2 * STEP];
+      const double v3 = col[3 * STEP], v4 = col[4 * STEP], v5 = col[5 * STEP];
+      if (m.scheme == AMR_SCHEME_CENTRAL) {
+        lv[q] = central4(v1, v2, v3, v4);
+        rv[q] = lv[q];
+      } else {
+        weno5_pair(v0, v1, v2, v3, v4, v5, eps4, lv[q], rv[q]);
+      }
+      lo[q] = v2;
+      hi[q] = v3;
+    }
+    const bool ok = (lv[0] > 0.0) && (lv[1] > 0.0) && (rv[0] > 0.0) && (rv[1] > 0.0);
+    wl.p = ok ? lv[0] : lo[0];
+    wl.T = ok ? lv[1] : lo[1];
+    wr.p = ok ? rv[0] : hi[0];
+    wr.T = ok ? rv[1] : hi[1];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      wl.u[i] = ok ? lv[2 + i] : lo[2 + i];
+      wr.u[i] = ok ? rv[2 + i] : hi[2 + i];
+    }
+    double UL[NV], FL[NV], UR[NV], FR[NV], sl, sr;
+    edge_flux<D, J>(m, wl, UL, FL, sl);
+    edge_flux<D, J>(m, wr, UR, FR, sr);
+    const double S = fmax(sr, sl);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
+  }
+  __syncthreads();
+
+  // 3. face fluxes G (flux form of Eq. (9)) and their divergence
+  const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
+  constexpr double c24 = 1.0 / 24.0;
+  const double half_inv_h = 0.5 * inv_h;
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int cell = tid + cc * NT;
+    if (cell >= S::NCELL) break;
+    const int t0 = cell % S::T0;
+    const int t1 = (cell / S::T0) % S::T1;
+    const int t2 = cell / (S::T0 * S::T1);
+    const int tj = J == 0 ? t0 : (J == 1 ? t1 : t2);
+    // edge-array index of edge (t_J - 2 + k) + 1/2 in the edge box
+    int eb;
+    constexpr int ESTEP = J == 0 ? 1 : (J == 1 ? G0 : G0 * G1);
+    if constexpr (J == 0) eb = G0 * (t1 + G1 * t2);
+    else if constexpr (J == 1) eb = t0 + G0 * G1 * t2;
+    else eb = t0 + G0 * t1;
+    eb += tj * ESTEP;
+    const int i = o[J] + tj;
+    int tang = 0;
+    if constexpr (D == 2) tang = (J == 0) ? (o[1] + t1) : (o[0] + t0);
+    if constexpr (D == 3) {
+      if constexpr (J == 0) tang = (o[1] + t1) + n * (o[2] + t2);
+      else if constexpr (J == 1) tang = (o[0] + t0) + n * (o[2] + t2);
+      else tang = (o[0] + t0) + n * (o[1] + t1);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      // edge fluxes are stored doubled (the Rusanov 1/2 is applied here, as
+      // 1/2 inv_h, and to the boundary faces; power-of-two scaling is exact)
+      const double* F = sF + v * NED + eb;
+      const double Fm2 = F[0], Fm1 = F[ESTEP], F0 = F[2 * ESTEP], Fp1 = F[3 * ESTEP];
+      const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
+      const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
+      acc[cc][v] = fma(-(Gp - Gm), half_inv_h, acc[cc][v]);
+      if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = 0.5 * Gm;
+      if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
+    }
+  }
+  __syncthreads();
+}
+
+template <int D, int TX, int TY, int TZ, int NT, bool FUSE>
+__global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+                                              const double* Un, double* out,
+                                              double* __restrict__ fr,
+                                              const int* __restrict__ tiles, int count,
+                                              const double* __restrict__ dtp,
+                                              unsigned long long* __restrict__ lam_next,
+                                              const uint8_t* __restrict__ cfmask) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int CPT = (S::NCELL + NT - 1) / NT;
+  constexpr bool UNION = D <= 2;
+  constexpr int NU = (S::T0 + 8) * (D >= 2 ? S::T1 + 8 : 1);
+  __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
+  __shared__ double sF[(D + 2) * S::EDMAX];
+  const int item = xcd_item(count);
+  if (item >= count) return;
+  const int pid = tiles[2 * item];
+  const int tix = tiles[2 * item + 1];
+  const int l = m.level[pid];
+  const LevelC& L = m.lv[l];
+  const int n = L.n, full = L.full;
+  const int nt0 = n / S::T0, nt1 = n / S::T1;
+  const int o[3] = {(tix % nt0) * S::T0, ((tix / nt0) % nt1) * S::T1, (tix / (nt0 * nt1)) * S::T2};
+  const long long base = patch_base(m, pid, l);
+  const double* Pin = Uin + base;
+  double* frp = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
+  double acc[CPT][NV];
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
+
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  if constexpr (UNION) {
+    load_union<D, TX, TY, NT, FUSE>(m, Uin, Pin, n, full, o, pc, l, sP);
+    __syncthreads();
+  }
+  stage_direction<D, TX, TY, TZ, NT, 0, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF,
+                                                     acc, L.inv_h);
+  if constexpr (D >= 2)
+    stage_direction<D, TX, TY, TZ, NT, 1, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
+                                                       sF, acc, L.inv_h);
+  if constexpr (D >= 3)
+    stage_direction<D, TX, TY, TZ, NT, 2, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
+                                                       sF, acc, L.inv_h);
+
+  const long long vs = var_stride<D>(full);
+  const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
+  constexpr double c23 = 2.0 / 3.0;
+  // next step's CFL rate from the final leaf values; cells on coarse/fine
+  // faces are left to the flux-correction kernel, which changes them
+  const bool want_rate = lam_next != nullptr && mode == kModeStage3;
+  const int fmask = want_rate ? cfmask[pid] : 0;
+  unsigned long long best = 0ull;
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int cell = threadIdx.x + cc * NT;
+    if (cell >= S::NCELL) break;
+    const int t0 = cell % S::T0;
+    const int t1 = (cell / S::T0) % S::T1;
+    const int t2 = cell / (S::T0 * S::T1);
+    const long long off = base + box_off<D>(full, o[0] + t0 + NG, o[1] + t1 + NG, o[2] + t2 + NG);
+    double r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const long long a = off + v * vs;
+      const double Lv = acc[cc][v];
+      if (mode == kModeRHS) {
+        r[v] = Lv;
+      } else if (mode == kModeStage1) {
+        r[v] = fma(dt, Lv, Un[a]);
+      } else {
+        const double un = Un[a];
+        const double ui = Uin[a];
+        r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
+      }
+      out[a] = r[v];
+    }
+    if (want_rate) {
+      const int c3[3] = {o[0] + t0, o[1] + t1, o[2] + t2};
+      bool on_cf = false;
+      for (int j = 0; j < D; ++j)
+        on_cf |= ((fmask >> (2 * j)) & 1) && c3[j] == 0 || ((fmask >> (2 * j + 1)) & 1) && c3[j] == n - 1;
+      if (!on_cf) {
+        const unsigned long long bits = cell_rate_bits<D>(r, m, L.h);
+        best = bits > best ? bits : best;
+      }
+    }
+  }
+  if (want_rate) block_max_atomic(best, lam_next);
+}
+
+}  // namespace
+
+static const Kernels::TileVariant kVariants[] = {
+    {1, 16, 1, 1, 64}, {1, 8, 1, 1, 64},                                   // 1D
+    {2, 16, 16, 1, 320}, {2, 16, 8, 1, 192}, {2, 8, 8, 1, 128},           // 2D
+    {3, 8, 8, 8, 704}, {3, 8, 8, 4, 448}, {3, 4, 4, 4, 128},              // 3D
+};
+
+int Kernels::num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+Kernels::TileVariant Kernels::variant(int v) { return kVariants[v]; }
+
+bool Kernels::variant_fits(int v, int dim, const int* n, int nlev) {
+  if (v < 0 || v >= num_variants() || kVariants[v].dim != dim) return false;
+  const TileVariant& t = kVariants[v];
+  for (int l = 0; l < nlev; ++l) {
+    if (n[l] % t.tx) return false;
+    if (dim >= 2 && n[l] % t.ty) return false;
+    if (dim >= 3 && n[l] % t.tz) return false;
+  }
+  return true;
+}
+
+int Kernels::default_variant(int dim, const int* n, int nlev) {
+  for (int v = 0; v < num_variants(); ++v)
+    if (variant_fits(v, dim, n, nlev)) return v;
+  return -1;
+}
+
+int Kernels::tiles_per_patch(int v, int n) {
+  const TileVariant& t = kVariants[v];
+  int r = n / t.tx;
+  if (t.dim >= 2) r *= n / t.ty;
+  if (t.dim >= 3) r *= n / t.tz;
+  return r;
+}
+
+void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
+                    double* out, double* fr, const int* tiles, int count, const double* dt,
+                    bool fuse, unsigned long long* lam_next, const uint8_t* cfmask,
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (count <= 0) return;
+  // one block per work item, rounded up to whole groups of kXcds blocks (see
+  // xcd_item)
+  const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
+#define AMR_STAGE_F(D, TX, TY, TZ, NT, F)                                                   \
+  do {                                                                                      \
+    if (ev0)                                                                                \
+      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, ev0,  \
+                            ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,  \
+                            cfmask);                                                        \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, m, mode, \
+                         Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);             \
+  } while (0)
+#define AMR_STAGE(D, TX, TY, TZ, NT)        \
+  do {                                      \
+    if (fuse)                               \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, true); \
+    else                                    \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, false);\
+  } while (0)
+  switch (m.tile) {
+    case 0: AMR_STAGE(1, 16, 1, 1, 64); break;
+    case 1: AMR_STAGE(1, 8, 1, 1, 64); break;
+    case 2: AMR_STAGE(2, 16, 16, 1, 320); break;
+    case 3: AMR_STAGE(2, 16, 8, 1, 192); break;
+    case 4: AMR_STAGE(2, 8, 8, 1, 128); break;
+    case 5: AMR_STAGE(3, 8, 8, 8, 704); break;
+    case 6: AMR_STAGE(3, 8, 8, 4, 448); break;
+    default: AMR_STAGE(3, 4, 4, 4, 128); break;
+  }
+#undef AMR_STAGE
+#undef AMR_STAGE_F
+}
+
+}  // namespace amr

@@ -232,7 +232,15 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                 tr, tc, _ = h.tag(0)
                 r = (pr | tr).cpu().numpy()
                 c = (pc & tc).cpu().numpy()
-                h.regrid(r, c)
+                try:
+                    h.regrid(r, c)
+                except A.AMRError as e:
+                    # the predicted refinement does not fit the patch pools
+                    # (the regrid left the mesh unchanged): plain regrid
+                    if e.status != A.E_CAPACITY:
+                        raise
+                    h.adapt()
+                    fallbacks += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells)
