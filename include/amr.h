@@ -277,7 +277,9 @@ amr_status amr_set_graph(amr_hierarchy* h, int enable);
 
 /* Tile variants of the fused stage kernel (cells per tile and block size):
  * 0: 16 (1D, 64 threads), 1: 8 (1D), 2: 16x16 (2D, 320), 3: 16x8 (2D, 192),
- * 4: 8x8 (2D, 128), 5: 8x8x8 (3D, 704), 6: 8x8x4 (3D, 448), 7: 4x4x4 (3D, 128).
+ * 4: 8x8 (2D, 128), 5: 8x8x8 (3D, 704), 6: 8x8x4 (3D, 448), 7: 4x4x4 (3D, 128);
+ * 8, 9, 10: 16x16, 16x8, 8x8 (2D) computing the x and y edge fluxes in one
+ * sweep (more LDS, fewer block barriers).
  * A variant is admissible when its extents divide every level's patch edge.
  * Every variant performs the same operations per cell: results are
  * identical.  amr_set_tile_variant (sync) selects one; amr_autotune (sync)
@@ -288,9 +290,10 @@ amr_status amr_get_tile_variant(const amr_hierarchy* h, int* variant, int* tx, i
                                 int* threads);
 amr_status amr_autotune(amr_hierarchy* h, int reps, int* best, float* best_ms);
 
-/* Halo source of the fused stage kernel: 1 (default) gathers halo nodes
- * outside a patch directly from same-level neighbours or by prolongation
- * (the ghost-fill rule, no separate fill pass); 0 runs the fill kernel first
+/* Halo source of the fused stage kernel: 1 (default) reads halo nodes that
+ * lie in same-level neighbours straight from those neighbours, and only the
+ * ghost cells that need prolongation are filled beforehand (over the ghost
+ * regions without a same-level source); 0 runs the full fill kernel first
  * and reads the filled ghost layers.  Results are identical. */
 amr_status amr_set_fused_halo(amr_hierarchy* h, int enable);
 

@@ -82,6 +82,10 @@ struct Kernels {
   static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
                      const int* list, int count, const double* dt, double w,
                      unsigned long long* lam_next, hipStream_t s);
+  // reflux items and the finest level's restriction items in one launch
+  static void post(const DevMesh& m, int mode, double* out, const double* fr, const int* rlist,
+                   int nref, const int* slist, int nres, const double* dt, double w,
+                   unsigned long long* lam_next, hipStream_t s);
   static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
                              hipStream_t s);
   static void max_rate(const DevMesh& m, const double* U, const int* list, int count,
@@ -105,6 +109,7 @@ struct Kernels {
   // Tile variants of the stage kernel: extents (cells) and block size.
   struct TileVariant {
     int dim, tx, ty, tz, threads;
+    int both = 0;  // 2D: x and y edges computed in one sweep
   };
   static int num_variants();
   static TileVariant variant(int v);

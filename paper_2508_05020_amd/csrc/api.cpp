@@ -458,11 +458,25 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
     Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
                    stage == 3 ? lam_next : nullptr, h->d_cfmask, h->stream, a, b);
   });
-  over_list(h, h->reflux, 2, [&](const int* p, int c) {
-    Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage],
-                    stage == 3 ? lam_next : nullptr, h->stream);
-  });
-  do_restrict(h, d);
+  if (h->exec_mode == AMR_EXEC_BATCHED) {
+    // refluxing and the finest restriction share a launch; coarser levels
+    // follow, finest first
+    const int fl = h->forest.nlev - 1;
+    const amr::ListView rs = fl >= 1 ? h->restr[fl] : amr::ListView{};
+    Kernels::post(h->dm, stage, h->U[d], h->fr, h->reflux.ptr, h->reflux.count, rs.ptr, rs.count,
+                  dt, w[stage], stage == 3 ? lam_next : nullptr, h->stream);
+    h->check_launch();
+    for (int l = fl - 1; l >= 1; --l)
+      over_list(h, h->restr[l], 1, [&](const int* p, int c) {
+        Kernels::restrict_level(h->dm, h->U[d], p, c, h->stream);
+      });
+  } else {
+    over_list(h, h->reflux, 2, [&](const int* p, int c) {
+      Kernels::reflux(h->dm, stage, h->U[d], h->fr, p, c, dt, w[stage],
+                      stage == 3 ? lam_next : nullptr, h->stream);
+    });
+    do_restrict(h, d);
+  }
 }
 
 // CFL rate of the leaf cells of buffer `buf` into rate slot `slot`

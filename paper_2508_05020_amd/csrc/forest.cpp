@@ -26,23 +26,49 @@ void Forest::init(const amr_config& cfg) {
     for (int j = 0; j < dim; ++j) m *= np[l];
     mapsize += m;
   }
-  // slot ranges: explicit capacities, else level 0 exact and the rest of
-  // max_patches shared equally by the finer levels (capped by level size)
-  long long used = 0;
+  // slot ranges: explicit capacities where given, level 0 exact otherwise;
+  // the remaining slots are shared equally by the other finer levels, a
+  // level never getting more than its patch count, with what a capped level
+  // leaves over shared again among the rest
   long long l0 = 1;
   for (int j = 0; j < dim; ++j) l0 *= np[0];
+  long long full[kMaxLev] = {}, c[kMaxLev] = {};
+  long long left = max_patches;
+  std::vector<int> open;
   for (int l = 0; l < nlev; ++l) {
-    long long full = 1;
-    for (int j = 0; j < dim; ++j) full *= np[l];
-    long long c = cfg.level_capacity[l];
-    if (c <= 0) {
-      if (l == 0) c = l0;
-      else c = std::max<long long>(1, (max_patches - l0) / std::max(1, nlev - 1));
+    full[l] = 1;
+    for (int j = 0; j < dim; ++j) full[l] *= np[l];
+    if (cfg.level_capacity[l] > 0) c[l] = std::min<long long>(cfg.level_capacity[l], full[l]);
+    else if (l == 0) c[l] = l0;
+    else {
+      open.push_back(l);
+      continue;
     }
-    c = std::min(c, full);
+    left -= c[l];
+  }
+  while (!open.empty()) {
+    const long long share = std::max<long long>(1, left / (long long)open.size());
+    std::vector<int> still;
+    for (int l : open) {
+      if (full[l] <= share) {
+        c[l] = full[l];
+        left -= c[l];
+      } else {
+        still.push_back(l);
+      }
+    }
+    if (still.size() == open.size()) {
+      for (int l : still) c[l] = share;
+      left -= share * (long long)still.size();
+      break;
+    }
+    open.swap(still);
+  }
+  long long used = 0;
+  for (int l = 0; l < nlev; ++l) {
     pid_base[l] = (int)used;
-    cap[l] = (int)c;
-    used += c;
+    cap[l] = (int)c[l];
+    used += c[l];
   }
   if (used > max_patches) throw std::invalid_argument("level capacities exceed max_patches");
   if (cap[0] < l0) throw std::invalid_argument("max_patches below the level-0 patch count");

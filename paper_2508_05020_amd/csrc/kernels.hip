@@ -137,12 +137,9 @@ __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __r
   const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
   const int nfface = (D == 1) ? 1 : (D == 2 ? nf : nf * nf);
   const int j = f >> 1, side = f & 1;
-  int tdim[2] = {0, 0}, nt = 0;
-  for (int k = 0; k < D; ++k)
-    if (k != j) tdim[nt++] = k;
   // fine cell column adjacent to the face (periodic wrap on the high side,
   // and on the low side of the domain)
-  int F = 2 * (pc[j] * n + (side ? n : 0));
+  int F = 2 * ((j == 0 ? pc[0] : (j == 1 ? pc[1] : pc[2])) * n + (side ? n : 0));
   int cj;
   if (side) {
     F %= Nf;
@@ -152,26 +149,45 @@ __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __r
     cj = F - 1;
   }
   const int fside = side ? 0 : 1;
-  int t = 0;
-  if constexpr (D >= 2) t = c[tdim[0]];
-  if constexpr (D >= 3) t += n * c[tdim[1]];
+  // tangential coordinates of the cell in ascending dimension order (all
+  // indexing below is by compile-time constants; j selects)
+  int tc[2] = {0, 0}, tp[2] = {0, 0};
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    if (d == j) continue;
+    const int k = d - (d > j ? 1 : 0);
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+      if (kk == k) {
+        tc[kk] = c[d];
+        tp[kk] = pc[d];
+      }
+  }
+  const int t = (D >= 2 ? tc[0] : 0) + (D >= 3 ? n * tc[1] : 0);
   double sub[4][NV];
-  const int nsub = 1 << (D - 1);
+  constexpr int nsub = 1 << (D - 1);
   bool ok = true;
+#pragma unroll
   for (int s = 0; s < nsub; ++s) {
-    int q[3] = {0, 0, 0}, fl[2] = {0, 0};
-    q[j] = cj / nf;
+    int qt[2] = {0, 0}, fl[2] = {0, 0};
+#pragma unroll
     for (int k = 0; k < D - 1; ++k) {
-      const int gfc = 2 * (pc[tdim[k]] * n + c[tdim[k]]) + ((s >> k) & 1);
-      q[tdim[k]] = gfc / nf;
-      fl[k] = gfc - q[tdim[k]] * nf;
+      const int gfc = 2 * (tp[k] * n + tc[k]) + ((s >> k) & 1);
+      qt[k] = gfc / nf;
+      fl[k] = gfc - qt[k] * nf;
+    }
+    // fine patch position: normal component cj / nf, tangential ones qt in
+    // ascending dimension order
+    int q[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int k = d - (d > j ? 1 : 0);
+      const int qtd = (k == 0) ? qt[0] : qt[1];
+      q[d] = (d == j) ? cj / nf : qtd;
     }
     const int fpid = map_at<D>(m, l + 1, q);
-    if (fpid < 0) {
-      ok = false;
-      break;
-    }
-    const double* frf = fr + Fv.fr_off + (long long)(fpid - Fv.pid_base) * Fv.fr_stride;
+    ok &= fpid >= 0;
+    const double* frf = fr + Fv.fr_off + (long long)((fpid < 0 ? Fv.pid_base : fpid) - Fv.pid_base) * Fv.fr_stride;
     const int ft = fl[0] + nf * fl[1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) sub[s][v] = frf[((j * 2 + fside) * NV + v) * nfface + ft];
@@ -196,15 +212,14 @@ __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __r
 // containing the cell in that order; at stage 3 it also feeds the corrected
 // cell's CFL rate to the next step's maximum.
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __restrict__ out,
-                                               const double* __restrict__ fr,
-                                               const int* __restrict__ list, int count,
-                                               const double* __restrict__ dtp, double w,
-                                               unsigned long long* __restrict__ lam_next) {
+__device__ __forceinline__ void reflux_item(const DevMesh& m, int mode, double* __restrict__ out,
+                                            const double* __restrict__ fr,
+                                            const int* __restrict__ list, int item,
+                                            const double* __restrict__ dtp, double w,
+                                            unsigned long long* __restrict__ lam_next) {
   constexpr int NV = D + 2;
-  if ((int)blockIdx.x >= count) return;
-  const int pid = list[2 * blockIdx.x];
-  const int mask = list[2 * blockIdx.x + 1];
+  const int pid = list[2 * item];
+  const int mask = list[2 * item + 1];
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n;
@@ -217,20 +232,23 @@ __global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __re
   const bool want_rate = lam_next != nullptr && mode == kModeStage3;
   auto on_face = [&](const int c[3], int g) {
     const int j = g >> 1;
-    return c[j] == ((g & 1) ? n - 1 : 0);
+    const int cj = (j == 0) ? c[0] : (j == 1 ? c[1] : c[2]);
+    return cj == ((g & 1) ? n - 1 : 0);
   };
   unsigned long long best = 0ull;
   for (int it = threadIdx.x; it < 2 * D * nface; it += NT) {
     const int f = it / nface, t = it - f * nface;
     if (!(mask & (1 << f))) continue;
     const int j = f >> 1;
+    // cell on face f: normal coordinate 0 or n-1, tangential ones from t in
+    // ascending dimension order
+    const int t0 = (D >= 2) ? t % n : 0, t1 = (D >= 3) ? t / n : 0;
     int c[3] = {0, 0, 0};
-    c[j] = (f & 1) ? n - 1 : 0;
-    int tdim[2] = {0, 0}, nt = 0;
-    for (int k = 0; k < D; ++k)
-      if (k != j) tdim[nt++] = k;
-    if constexpr (D >= 2) c[tdim[0]] = t % n;
-    if constexpr (D >= 3) c[tdim[1]] = t / n;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int k = d - (d > j ? 1 : 0);
+      c[d] = (d == j) ? ((f & 1) ? n - 1 : 0) : (k == 0 ? t0 : t1);
+    }
     bool owned = true;
     for (int g = 0; g < f; ++g) owned &= !((mask & (1 << g)) && on_face(c, g));
     if (!owned) continue;
@@ -249,12 +267,23 @@ __global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __re
   if (want_rate) block_max_atomic(best, lam_next);
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
-                                                  const int* __restrict__ list, int count) {
-  constexpr int NV = D + 2;
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __restrict__ out,
+                                               const double* __restrict__ fr,
+                                               const int* __restrict__ list, int count,
+                                               const double* __restrict__ dtp, double w,
+                                               unsigned long long* __restrict__ lam_next) {
   if ((int)blockIdx.x >= count) return;
-  const int cpid = list[blockIdx.x];
+  reflux_item<D, NT>(m, mode, out, fr, list, blockIdx.x, dtp, w, lam_next);
+}
+
+// Restriction of one child patch into the covered cells of its parent:
+// pairwise sums in x, then y, then z order, times 2^-D.
+template <int D>
+__device__ __forceinline__ void restrict_item(const DevMesh& m, double* __restrict__ U,
+                                              const int* __restrict__ list, int item) {
+  constexpr int NV = D + 2;
+  const int cpid = list[item];
   const int lf = m.level[cpid];
   const int ppid = m.parent[cpid];
   const LevelC& F = m.lv[lf];
@@ -289,6 +318,29 @@ __global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict_
       Pp[v * vsc + dst] = r;
     }
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
+                                                  const int* __restrict__ list, int count) {
+  if ((int)blockIdx.x >= count) return;
+  restrict_item<D>(m, U, list, blockIdx.x);
+}
+
+// After a stage: refluxing and the restriction of the finest level in one
+// launch (blocks [0, nref) reflux, the rest restrict).  The two touch
+// disjoint cells: refluxing changes leaf cells below the finest level, the
+// finest restriction reads finest-level cells and writes non-leaf cells.
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode, double* __restrict__ out,
+                                             const double* __restrict__ fr,
+                                             const int* __restrict__ rlist, int nref,
+                                             const int* __restrict__ slist, int nres,
+                                             const double* __restrict__ dtp, double w,
+                                             unsigned long long* __restrict__ lam_next) {
+  const int b = blockIdx.x;
+  if (b < nref) reflux_item<D, NT>(m, mode, out, fr, rlist, b, dtp, w, lam_next);
+  else if (b - nref < nres) restrict_item<D>(m, out, slist, b - nref);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +612,18 @@ void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
     case 1: k_reflux<1, 64><<<count, 64, 0, s>>>(m, mode, out, fr, list, count, dt, w, lam_next); break;
     case 2: k_reflux<2, 64><<<count, 64, 0, s>>>(m, mode, out, fr, list, count, dt, w, lam_next); break;
     default: k_reflux<3, 256><<<count, 256, 0, s>>>(m, mode, out, fr, list, count, dt, w, lam_next); break;
+  }
+}
+
+void Kernels::post(const DevMesh& m, int mode, double* out, const double* fr,
+                   const int* rlist, int nref, const int* slist, int nres, const double* dt,
+                   double w, unsigned long long* lam_next, hipStream_t s) {
+  const int nb = nref + nres;
+  if (nb <= 0) return;
+  switch (m.dim) {
+    case 1: k_post<1, 64><<<nb, 64, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
+    case 2: k_post<2, 64><<<nb, 64, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
+    default: k_post<3, 256><<<nb, 256, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
   }
 }
 

@@ -39,6 +39,21 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
+// sqrt(x) for x > 0 from the hardware reciprocal square-root estimate
+// (relative error near 2^-24): one coupled Goldschmidt step for sqrt(x) and
+// 1/(2 sqrt(x)), then one Newton correction of the root (a few ulp).  Used
+// for the sound speed in the Rusanov dissipation only.
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // Nonlinear WENO5-JS combination of three candidates from their smoothness
 // indicators.  The weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
 // t_k = (eps + beta_k)^2 and d = (1, 10, 5)/16 are evaluated as cross
@@ -119,7 +134,7 @@ __device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& 
   }
   U[D + 1] = E;
   F[D + 1] = (E + w.p) * w.u[J];
-  speed = sqrt(m.gamma * w.T) + fabs(w.u[J]);
+  speed = sqrt_nr(m.gamma * w.T) + fabs(w.u[J]);
 }
 
 template <int D, int TX, int TY, int TZ>
@@ -156,24 +171,70 @@ __device__ __forceinline__ void node_primitives(const DevMesh& m, const double* 
   q[1] = p * r;
 }
 
+// Same-level patches around the tile's patch, by offset code
+// (o0+1) + 3 (o1+1) + 9 (o2+1), o in {-1,0,1}^D (periodic wrap; -1 where no
+// patch or outside a non-periodic domain), looked up once per block.
+template <int D>
+__device__ __forceinline__ void load_neighbours(const DevMesh& m, int l, const int pc[3],
+                                                int* sN) {
+  constexpr int NO = D == 1 ? 3 : (D == 2 ? 9 : 27);
+  const int t = threadIdx.x;
+  if (t < NO) {
+    const int np = m.lv[l].np;
+    int q[3] = {0, 0, 0};
+    bool in = true;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int o = (j == 0 ? t : (j == 1 ? t / 3 : t / 9)) % 3 - 1;
+      int v = pc[j] + o;
+      if (v < 0 || v >= np) {
+        if (m.periodic[j]) v = (v + np) % np;
+        else in = false;
+      }
+      q[j] = v;
+    }
+    sN[t] = in ? map_at<D>(m, l, q) : -1;
+  }
+}
+
 // Conserved values of a node at patch-local cell c (may lie in the halo):
-// from the patch itself, or by the ghost-fill rule when outside the patch.
+// from the patch itself, or by the ghost-fill rule when outside the patch
+// (same-level source from the neighbour table sN, else the patch's own ghost
+// layer, which holds the prolonged value).
 template <int D, bool FUSE>
 __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* __restrict__ Uin,
                                                const double* __restrict__ Pin, int n, int full,
                                                const int c[3], const int pc[3], int l,
-                                               double* u) {
+                                               const int* sN, double* u) {
   constexpr int NV = D + 2;
   bool inside = true;
   for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
+  const long long vs = var_stride<D>(full);
   if (FUSE && !inside) {
-    int g[3] = {0, 0, 0};
-    for (int j = 0; j < D; ++j) g[j] = bc_map(pc[j] * n + c[j], m.lv[l].cells, m.periodic[j]);
-    if (fetch_cell<D>(m, Uin, l, g, u)) return;
+    const LevelC& L = m.lv[l];
+    int code = 0, loc[3] = {0, 0, 0}, mul = 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int g = bc_map(pc[j] * n + c[j], L.cells, m.periodic[j]);
+      const int q = g / n;
+      int o = q - pc[j];
+      if (o > 1) o -= L.np;
+      if (o < -1) o += L.np;
+      loc[j] = g - q * n;
+      code += (o + 1) * mul;
+      mul *= 3;
+    }
+    const int src = sN[code];
+    if (src >= 0) {
+      const double* S = Uin + patch_base(m, src, l);
+      const long long off = box_off<D>(full, loc[0] + NG, loc[1] + NG, loc[2] + NG);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = S[v * vs + off];
+      return;
+    }
     // no same-level source: the prolonged ghost value was written into the
     // patch's own ghost layer by the coarse-ghost fill pass
   }
-  const long long vs = var_stride<D>(full);
   const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
@@ -184,7 +245,8 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
 template <int D, int TX, int TY, int NT, bool FUSE>
 __device__ __forceinline__ void load_union(const DevMesh& m, const double* __restrict__ Uin,
                                            const double* __restrict__ Pin, int n, int full,
-                                           const int o[3], const int pc[3], int l, double* sP) {
+                                           const int o[3], const int pc[3], int l,
+                                           const int* sN, double* sP) {
   constexpr int T0 = TX, T1 = D >= 2 ? TY : 1;
   constexpr int U0 = T0 + 8, U1 = D >= 2 ? T1 + 8 : 1;
   constexpr int NU = U0 * U1;
@@ -196,100 +258,70 @@ __device__ __forceinline__ void load_union(const DevMesh& m, const double* __res
     if (hx && hy) continue;
     const int c[3] = {o[0] + e0 - 4, D >= 2 ? o[1] + e1 - 4 : 0, 0};
     double u[D + 2], q[NQ];
-    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
+    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u);
     node_primitives<D>(m, u, q);
 #pragma unroll
     for (int k = 0; k < NQ; ++k) sP[k * NU + idx] = q[k];
   }
 }
 
-template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool UNION>
-__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
-                                                const double* __restrict__ Pin,
-                                                double* __restrict__ frp, int n, int full,
-                                                const int o[3], const int pc[3], int l,
-                                                double* sP, double* sF,
-                                                double acc[][D + 2], double inv_h) {
-  using S = TileShape<D, TX, TY, TZ>;
+// Riemann flux of direction J at one edge whose window (nodes i-2 .. i+3)
+// starts at layout index `base` of the primitives in LDS (NEXT nodes per
+// primitive, STEP between neighbours along J); stored doubled at sF[v NED + e].
+template <int D, int J, int NEXT, int STEP, int NED>
+__device__ __forceinline__ void edge_at(const DevMesh& m, const double* sP, int base, double* sF,
+                                        int e) {
   constexpr int NV = D + 2;
   constexpr int NQ = D + 2;  // interpolated primitives: p, T, u_j
-  constexpr int E0 = UNION ? S::T0 + 8 : S::T0 + (J == 0 ? 8 : 0);
-  constexpr int E1 = UNION ? (D >= 2 ? S::T1 + 8 : 1) : S::T1 + (J == 1 ? 8 : 0);
-  constexpr int E2 = UNION ? 1 : S::T2 + (J == 2 ? 8 : 0);
-  constexpr int NEXT = E0 * E1 * E2;
+  EdgeState<D> wl, wr;
+  double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
+  const double eps4 = 4.0 * m.eps;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double* col = sP + q * NEXT + base;
+    const double v0 = col[0], v1 = col[STEP], v2 = col[2 * STEP];
+    const double v3 = col[3 * STEP], v4 = col[4 * STEP], v5 = col[5 * STEP];
+    if (m.scheme == AMR_SCHEME_CENTRAL) {
+      lv[q] = central4(v1, v2, v3, v4);
+      rv[q] = lv[q];
+    } else {
+      weno5_pair(v0, v1, v2, v3, v4, v5, eps4, lv[q], rv[q]);
+    }
+    lo[q] = v2;
+    hi[q] = v3;
+  }
+  const bool ok = (lv[0] > 0.0) && (lv[1] > 0.0) && (rv[0] > 0.0) && (rv[1] > 0.0);
+  wl.p = ok ? lv[0] : lo[0];
+  wl.T = ok ? lv[1] : lo[1];
+  wr.p = ok ? rv[0] : hi[0];
+  wr.T = ok ? rv[1] : hi[1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    wl.u[i] = ok ? lv[2 + i] : lo[2 + i];
+    wr.u[i] = ok ? rv[2 + i] : hi[2 + i];
+  }
+  double UL[NV], FL[NV], UR[NV], FR[NV], sl, sr;
+  edge_flux<D, J>(m, wl, UL, FL, sl);
+  edge_flux<D, J>(m, wr, UR, FR, sr);
+  const double S = fmax(sr, sl);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
+}
+
+// Face fluxes G of direction J (flux form of Eq. (9)) from the edge fluxes
+// in sF, their divergence into acc, and the patch-boundary faces into the
+// flux registers.
+template <int D, int TX, int TY, int TZ, int NT, int J>
+__device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ frp, int n,
+                                         const int o[3], double acc[][D + 2], double inv_h) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
   constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
   constexpr int G1 = S::T1 + (J == 1 ? 3 : 0);
   constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
   constexpr int NED = G0 * G1 * G2;
-  constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
   const int tid = threadIdx.x;
-
-  // 1. primitives of the tile extended by 4 nodes on both sides along J
-  // (the union layout is loaded once by the caller for all directions)
-  if constexpr (!UNION) {
-    for (int idx = tid; idx < NEXT; idx += NT) {
-      const int e0 = idx % E0;
-      const int e1 = (idx / E0) % E1;
-      const int e2 = idx / (E0 * E1);
-      const int c[3] = {o[0] + e0 - (J == 0 ? 4 : 0), o[1] + e1 - (J == 1 ? 4 : 0),
-                        o[2] + e2 - (J == 2 ? 4 : 0)};
-      double u[NV], q[NQ];
-      node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, u);
-      node_primitives<D>(m, u, q);
-#pragma unroll
-      for (int k = 0; k < NQ; ++k) sP[k * NEXT + idx] = q[k];
-    }
-    __syncthreads();
-  }
-
-  // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
-  for (int e = tid; e < NED; e += NT) {
-    const int a0 = e % G0;
-    const int a1 = (e / G0) % G1;
-    const int a2 = e / (G0 * G1);
-    // layout index of node i-2 of this edge's window
-    int base;
-    if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);
-    else if constexpr (J == 0) base = (D >= 2 ? (a1 + 4) * E0 : 0) + a0;
-    else base = a1 * E0 + (a0 + 4);
-    EdgeState<D> wl, wr;
-    double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
-    const double eps4 = 4.0 * m.eps;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const double* col = sP + q * NEXT + base;
-      const double v0 = col[0], v1 = col[STEP], v2 = col[2 * STEP];
-      const double v3 = col[3 * STEP], v4 = col[4 * STEP], v5 = col[5 * STEP];
-      if (m.scheme == AMR_SCHEME_CENTRAL) {
-        lv[q] = central4(v1, v2, v3, v4);
-        rv[q] = lv[q];
-      } else {
-        weno5_pair(v0, v1, v2, v3, v4, v5, eps4, lv[q], rv[q]);
-      }
-      lo[q] = v2;
-      hi[q] = v3;
-    }
-    const bool ok = (lv[0] > 0.0) && (lv[1] > 0.0) && (rv[0] > 0.0) && (rv[1] > 0.0);
-    wl.p = ok ? lv[0] : lo[0];
-    wl.T = ok ? lv[1] : lo[1];
-    wr.p = ok ? rv[0] : hi[0];
-    wr.T = ok ? rv[1] : hi[1];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      wl.u[i] = ok ? lv[2 + i] : lo[2 + i];
-      wr.u[i] = ok ? rv[2 + i] : hi[2 + i];
-    }
-    double UL[NV], FL[NV], UR[NV], FR[NV], sl, sr;
-    edge_flux<D, J>(m, wl, UL, FL, sl);
-    edge_flux<D, J>(m, wr, UR, FR, sr);
-    const double S = fmax(sr, sl);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
-  }
-  __syncthreads();
-
-  // 3. face fluxes G (flux form of Eq. (9)) and their divergence
   const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
   constexpr double c24 = 1.0 / 24.0;
   const double half_inv_h = 0.5 * inv_h;
@@ -329,11 +361,96 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
       if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
     }
   }
+}
+
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool UNION>
+__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
+                                                const double* __restrict__ Pin,
+                                                double* __restrict__ frp, int n, int full,
+                                                const int o[3], const int pc[3], int l,
+                                                const int* sN, double* sP, double* sF,
+                                                double acc[][D + 2], double inv_h) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int NQ = D + 2;
+  constexpr int E0 = UNION ? S::T0 + 8 : S::T0 + (J == 0 ? 8 : 0);
+  constexpr int E1 = UNION ? (D >= 2 ? S::T1 + 8 : 1) : S::T1 + (J == 1 ? 8 : 0);
+  constexpr int E2 = UNION ? 1 : S::T2 + (J == 2 ? 8 : 0);
+  constexpr int NEXT = E0 * E1 * E2;
+  constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
+  constexpr int G1 = S::T1 + (J == 1 ? 3 : 0);
+  constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
+  constexpr int NED = G0 * G1 * G2;
+  constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
+  const int tid = threadIdx.x;
+
+  // 1. primitives of the tile extended by 4 nodes on both sides along J
+  // (the union layout is loaded once by the caller for all directions)
+  if constexpr (!UNION) {
+    for (int idx = tid; idx < NEXT; idx += NT) {
+      const int e0 = idx % E0;
+      const int e1 = (idx / E0) % E1;
+      const int e2 = idx / (E0 * E1);
+      const int c[3] = {o[0] + e0 - (J == 0 ? 4 : 0), o[1] + e1 - (J == 1 ? 4 : 0),
+                        o[2] + e2 - (J == 2 ? 4 : 0)};
+      double u[NV], q[NQ];
+      node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u);
+      node_primitives<D>(m, u, q);
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) sP[k * NEXT + idx] = q[k];
+    }
+    __syncthreads();
+  }
+
+  // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
+  for (int e = tid; e < NED; e += NT) {
+    const int a0 = e % G0;
+    const int a1 = (e / G0) % G1;
+    const int a2 = e / (G0 * G1);
+    // layout index of node i-2 of this edge's window
+    int base;
+    if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);
+    else if constexpr (J == 0) base = (D >= 2 ? (a1 + 4) * E0 : 0) + a0;
+    else base = a1 * E0 + (a0 + 4);
+    edge_at<D, J, NEXT, STEP, NED>(m, sP, base, sF, e);
+  }
+  __syncthreads();
+
+  // 3. face fluxes G and their divergence
+  cells_at<D, TX, TY, TZ, NT, J>(sF, frp, n, o, acc, inv_h);
   __syncthreads();
 }
 
-template <int D, int TX, int TY, int TZ, int NT, bool FUSE>
-__global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+// 2D union layout, both directions at once: the x and y edges form one work
+// range (x first), then every cell takes its x and then its y divergence,
+// the order of the direction-by-direction path.
+template <int D, int TX, int TY, int NT>
+__device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict__ frp, int n,
+                                           const int o[3], const double* sP, double* sFx,
+                                           double* sFy, double acc[][D + 2], double inv_h) {
+  static_assert(D == 2, "combined sweep is 2D");
+  using S = TileShape<D, TX, TY, 1>;
+  constexpr int E0 = S::T0 + 8, E1 = S::T1 + 8;
+  constexpr int NEXT = E0 * E1;
+  constexpr int GX0 = S::T0 + 3, NEDX = GX0 * S::T1;
+  constexpr int GY0 = S::T0, NEDY = S::T0 * (S::T1 + 3);
+  for (int e = threadIdx.x; e < NEDX + NEDY; e += NT) {
+    if (e < NEDX) {
+      const int a0 = e % GX0, a1 = e / GX0;
+      edge_at<D, 0, NEXT, 1, NEDX>(m, sP, (a1 + 4) * E0 + a0, sFx, e);
+    } else {
+      const int f = e - NEDX;
+      const int a0 = f % GY0, a1 = f / GY0;
+      edge_at<D, 1, NEXT, E0, NEDY>(m, sP, a1 * E0 + (a0 + 4), sFy, f);
+    }
+  }
+  __syncthreads();
+  cells_at<D, TX, TY, 1, NT, 0>(sFx, frp, n, o, acc, inv_h);
+  cells_at<D, TX, TY, 1, NT, 1>(sFy, frp, n, o, acc, inv_h);
+}
+
+template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 : 1))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
                                               const int* __restrict__ tiles, int count,
@@ -345,8 +462,10 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
   constexpr bool UNION = D <= 2;
   constexpr int NU = (S::T0 + 8) * (D >= 2 ? S::T1 + 8 : 1);
+  // edge fluxes: one direction at a time, or x and y together (BOTH)
+  constexpr int NEDXY = (S::T0 + 3) * S::T1 + S::T0 * (S::T1 + 3);
   __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
-  __shared__ double sF[(D + 2) * S::EDMAX];
+  __shared__ double sF[(D + 2) * (BOTH ? NEDXY : S::EDMAX)];
   const int item = xcd_item(count);
   if (item >= count) return;
   const int pid = tiles[2 * item];
@@ -366,18 +485,28 @@ __global__ __launch_bounds__(NT) void k_stage(DevMesh m, int mode, const double*
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
-  if constexpr (UNION) {
-    load_union<D, TX, TY, NT, FUSE>(m, Uin, Pin, n, full, o, pc, l, sP);
+  __shared__ int sN[27];
+  if constexpr (FUSE) {
+    load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
   }
-  stage_direction<D, TX, TY, TZ, NT, 0, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP, sF,
-                                                     acc, L.inv_h);
-  if constexpr (D >= 2)
-    stage_direction<D, TX, TY, TZ, NT, 1, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
-                                                       sF, acc, L.inv_h);
-  if constexpr (D >= 3)
-    stage_direction<D, TX, TY, TZ, NT, 2, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sP,
-                                                       sF, acc, L.inv_h);
+  if constexpr (UNION) {
+    load_union<D, TX, TY, NT, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    __syncthreads();
+  }
+  if constexpr (BOTH && D == 2) {
+    stage_both<D, TX, TY, NT>(m, frp, n, o, sP, sF, sF + (D + 2) * ((S::T0 + 3) * S::T1), acc,
+                              L.inv_h);
+  } else {
+    stage_direction<D, TX, TY, TZ, NT, 0, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
+                                                       sP, sF, acc, L.inv_h);
+    if constexpr (D >= 2)
+      stage_direction<D, TX, TY, TZ, NT, 1, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
+                                                         sP, sF, acc, L.inv_h);
+    if constexpr (D >= 3)
+      stage_direction<D, TX, TY, TZ, NT, 2, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
+                                                         sP, sF, acc, L.inv_h);
+  }
 
   const long long vs = var_stride<D>(full);
   const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
@@ -431,6 +560,8 @@ static const Kernels::TileVariant kVariants[] = {
     {1, 16, 1, 1, 64}, {1, 8, 1, 1, 64},                                   // 1D
     {2, 16, 16, 1, 320}, {2, 16, 8, 1, 192}, {2, 8, 8, 1, 128},           // 2D
     {3, 8, 8, 8, 704}, {3, 8, 8, 4, 448}, {3, 4, 4, 4, 128},              // 3D
+    // 2D, x and y edges in one sweep (stage_both)
+    {2, 16, 16, 1, 320, 1}, {2, 16, 8, 1, 192, 1}, {2, 8, 8, 1, 128, 1},
 };
 
 int Kernels::num_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -470,32 +601,35 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
   // one block per work item, rounded up to whole groups of kXcds blocks (see
   // xcd_item)
   const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
-#define AMR_STAGE_F(D, TX, TY, TZ, NT, F)                                                   \
-  do {                                                                                      \
-    if (ev0)                                                                                \
-      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, ev0,  \
-                            ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,  \
-                            cfmask);                                                        \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F>), dim3(nb), dim3(NT), 0, s, m, mode, \
-                         Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);             \
+#define AMR_STAGE_F(D, TX, TY, TZ, NT, F, B)                                                \
+  do {                                                                                       \
+    if (ev0)                                                                                 \
+      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, ev0, \
+                            ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,   \
+                            cfmask);                                                         \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, m,     \
+                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);        \
   } while (0)
-#define AMR_STAGE(D, TX, TY, TZ, NT)        \
-  do {                                      \
-    if (fuse)                               \
-      AMR_STAGE_F(D, TX, TY, TZ, NT, true); \
-    else                                    \
-      AMR_STAGE_F(D, TX, TY, TZ, NT, false);\
+#define AMR_STAGE(D, TX, TY, TZ, NT, B)        \
+  do {                                         \
+    if (fuse)                                  \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, true, B); \
+    else                                       \
+      AMR_STAGE_F(D, TX, TY, TZ, NT, false, B);\
   } while (0)
   switch (m.tile) {
-    case 0: AMR_STAGE(1, 16, 1, 1, 64); break;
-    case 1: AMR_STAGE(1, 8, 1, 1, 64); break;
-    case 2: AMR_STAGE(2, 16, 16, 1, 320); break;
-    case 3: AMR_STAGE(2, 16, 8, 1, 192); break;
-    case 4: AMR_STAGE(2, 8, 8, 1, 128); break;
-    case 5: AMR_STAGE(3, 8, 8, 8, 704); break;
-    case 6: AMR_STAGE(3, 8, 8, 4, 448); break;
-    default: AMR_STAGE(3, 4, 4, 4, 128); break;
+    case 0: AMR_STAGE(1, 16, 1, 1, 64, false); break;
+    case 1: AMR_STAGE(1, 8, 1, 1, 64, false); break;
+    case 2: AMR_STAGE(2, 16, 16, 1, 320, false); break;
+    case 3: AMR_STAGE(2, 16, 8, 1, 192, false); break;
+    case 4: AMR_STAGE(2, 8, 8, 1, 128, false); break;
+    case 5: AMR_STAGE(3, 8, 8, 8, 704, false); break;
+    case 6: AMR_STAGE(3, 8, 8, 4, 448, false); break;
+    case 7: AMR_STAGE(3, 4, 4, 4, 128, false); break;
+    case 8: AMR_STAGE(2, 16, 16, 1, 320, true); break;
+    case 9: AMR_STAGE(2, 16, 8, 1, 192, true); break;
+    default: AMR_STAGE(2, 8, 8, 1, 128, true); break;
   }
 #undef AMR_STAGE
 #undef AMR_STAGE_F

@@ -109,11 +109,13 @@ class Dataset:
 
 
 def build_dataset(resolutions: Sequence[int], seeds: Sequence[int], steps: int, horizon: int,
-                  stride: int, mean, std, n: int = 32) -> Dataset:
+                  stride: int, mean, std, n: int = 32, tag_buffer: int = 2) -> Dataset:
+    """Inputs and labels of single-level runs at the given resolutions, the
+    labels dilated by `tag_buffer` cells like the tagger they forecast."""
     torch = A._torch()
     xs, ys = [], []
     for base in resolutions:
-        cfg = uniform_config(base, n)
+        cfg = uniform_config(base, n, tag_buffer=tag_buffer)
         for seed in seeds:
             x, y = record(cfg, seed, steps, horizon, stride, mean, std)
             xs.append(x)
@@ -161,7 +163,8 @@ def choose_tau(pred: A.Predictor, data: Dataset, recall: float = 0.995) -> float
         return 0.5
     zs = np.sort(s[pos])
     k = int(math.floor((1.0 - recall) * len(zs)))
-    zt = zs[k] - 1e-3
+    # the threshold as a probability strictly inside (0, 1) in float32 terms
+    zt = float(np.clip(zs[k] - 1e-3, -15.0, 15.0))
     return float(1.0 / (1.0 + math.exp(-zt)))
 
 
@@ -202,9 +205,29 @@ class RunStats:
         return d
 
 
+def learned_regrid(h: A.Hierarchy, pred: A.Predictor, tau: float, rounds: int = 1) -> int:
+    """Up to `rounds` regrids with refine = predicted | plain tags and
+    coarsen = predicted-quiet & plain coarsen requests (the first round only
+    coarsens), each round predicting on the leaves the previous one created;
+    returns the number of rounds that changed the mesh."""
+    changed = 0
+    for r in range(rounds):
+        pr, pc = pred.predict(0, tau)
+        tr, tc, _ = h.tag(0)
+        ref = (pr | tr).cpu().numpy()
+        coa = (pc & tc).cpu().numpy() if r == 0 else np.zeros_like(ref)
+        if not ref.any() and not coa.any():
+            break
+        nc, nd = h.regrid(ref, coa)
+        if nc == 0 and nd == 0:
+            break
+        changed += 1
+    return changed
+
+
 def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                pred: Optional[A.Predictor] = None, tau: float = 0.5,
-               judge: bool = False) -> RunStats:
+               judge: bool = False, rounds: int = 1) -> RunStats:
     """Advance `steps` steps under a regrid policy; wall time includes
     tagging, prediction, judging and regridding."""
     torch = A._torch()
@@ -228,12 +251,8 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
             if policy == "plain":
                 h.adapt()
             else:
-                pr, pc = pred.predict(0, tau)
-                tr, tc, _ = h.tag(0)
-                r = (pr | tr).cpu().numpy()
-                c = (pc & tc).cpu().numpy()
                 try:
-                    h.regrid(r, c)
+                    learned_regrid(h, pred, tau, rounds)
                 except A.AMRError as e:
                     # the predicted refinement does not fit the patch pools
                     # (the regrid left the mesh unchanged): plain regrid

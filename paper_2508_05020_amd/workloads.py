@@ -109,7 +109,7 @@ CONFIGS = {
     # 3D blast waves, 4 levels, uneven 32/16/16/8 patches, periodic.
     "c3": _cfg(name="c3", dim=3, base_cells=128, patch_cells=[32, 16, 16, 8],
                periodic=[True] * 3, steps=50, regrid_interval=4, ic="blasts",
-               max_patches=65536),
+               max_patches=98304),
     # 2D quadrants + blobs on 512^2, 5 levels of 32^2 patches.
     "c4": _cfg(name="c4", dim=2, base_cells=512, patch_cells=[32] * 5,
                periodic=[True, True], steps=200, regrid_interval=8,

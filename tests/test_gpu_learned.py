@@ -1,0 +1,82 @@
+"""What the trained refinement predictor gains over regridding without it
+(GPU).  The network is trained by the library's own kernels on tags that the
+solver generates (single-level runs at the resolutions of the hierarchy's
+levels, labels = the plain tags of the next 16 steps), then the same seeded
+4-level run advances 128 steps under three regrid policies, each under the
+plain-tag judge with fallback (after every step the plain tagger checks that
+every tagged cell lies in a finest-level leaf, and a plain regrid follows at
+once when one does not):
+
+  plain every 2 steps, plain every 16 steps, learned every 16 steps.
+
+The gain is counted in judge failures and regrid operations, which do not
+depend on timing: the learned policy needs fewer fallbacks than plain
+regridding at the same interval, and far fewer regrids in total than plain
+regridding every 2 steps.  Wall-clock figures are printed, not asserted."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N = 16
+H = 16
+STEPS = 128
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2508_05020_amd import amr, learned, workloads as W
+    cfg = W.AMRConfig(name="learned-eval", dim=2, base_cells=64, patch_cells=[N] * 4,
+                      periodic=[True, True], ic="quadrants_blobs", tag_buffer=1,
+                      max_patches=16384)
+    seeds = [4000, 4001, 4002]
+    resolutions = (64, 128, 256, 512)
+    mean, std = learned.input_statistics([learned.uniform_config(64, N, tag_buffer=1)],
+                                         seeds[:1], steps=8)
+    data = learned.build_dataset(resolutions, seeds, steps=40, horizon=H, stride=2, mean=mean,
+                                 std=std, n=N, tag_buffer=1)
+    val = learned.build_dataset(resolutions[-2:], [4100], steps=40, horizon=H, stride=4,
+                                mean=mean, std=std, n=N, tag_buffer=1)
+    pos = float(data.y.mean())
+    pos_weight = float(min(100.0, (1.0 - pos) / max(pos, 1e-6)))
+    return amr, learned, W, cfg, data, val, mean, std, pos_weight
+
+
+def _hier(amr, W, cfg, seed=4100):
+    h = amr.Hierarchy(cfg)
+    amr.init_from_ic(h, W.initial_data(cfg, seed))
+    return h
+
+
+def test_learned_regridding_gain(setup):
+    amr, learned, W, cfg, data, val, mean, std, pos_weight = setup
+    # warm-up run (graph capture, allocator) outside the comparison
+    h = _hier(amr, W, cfg)
+    learned.run_policy(h, 8, 2, "plain", judge=True)
+    h.close()
+
+    h_bl = _hier(amr, W, cfg)
+    pred = amr.Predictor(h_bl, N, mean, std, pos_weight=pos_weight, max_batch=256)
+    pred.set_weights(learned.init_weights(seed=1))
+    losses = learned.train(pred, data, epochs=30, lr=2e-3, batch=64)
+    assert losses[-1] < 0.5 * losses[0], losses
+    tau = learned.choose_tau(pred, val, recall=0.99)
+    print("validation", learned.patch_metrics(pred, val, tau), "tau", tau)
+    pred.predict(0, tau)  # first use of the inference kernels
+
+    runs = {}
+    for name, every, policy in (("plain2", 2, "plain"), ("plain16", H, "plain"),
+                                ("learned16", H, "learned")):
+        h = h_bl if policy == "learned" else _hier(amr, W, cfg)
+        runs[name] = learned.run_policy(h, STEPS, every, policy,
+                                        pred if policy == "learned" else None, tau, judge=True)
+        print(name, runs[name].as_dict())
+    p2, p16, l16 = runs["plain2"], runs["plain16"], runs["learned16"]
+    # the three runs cover the same physical time (global dt from the same
+    # physics to round-off; meshes differ only where refinement differs)
+    assert abs(l16.t_sim - p2.t_sim) <= 0.02 * p2.t_sim
+    # forecasting: fewer judge failures than plain regridding at the same
+    # interval
+    assert l16.fallbacks < p16.fallbacks, (l16.as_dict(), p16.as_dict())
+    # and far fewer regrid operations than plain regridding every 2 steps
+    assert l16.regrids + l16.fallbacks < 0.5 * (p2.regrids + p2.fallbacks)
+    pred.close()
