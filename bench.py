@@ -204,6 +204,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every kernel of a step eagerly instead of replaying a hipGraph")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this stage-kernel tile variant instead of autotuning")
     ap.add_argument("--learned", action="store_true",
@@ -239,6 +241,8 @@ def main() -> int:
     amr.init_from_ic(h, workloads.initial_data(cfg, args.seed))
     log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
         f"{h.leaf_cells()} leaf cells")
+    if args.no_graph:
+        h.set_graph(False)
     tile = None
     if args.tile is not None:
         h.set_tile_variant(args.tile)
@@ -318,6 +322,7 @@ def main() -> int:
                         f"{'periodic' if all(cfg.periodic) else 'mixed bc'}, ic {cfg.ic} "
                         f"seed {args.seed}, CFL {cfg.cfl}, regrid every {cfg.regrid_interval}",
             "exec": args.exec_mode,
+            "step_graph": mode == amr.EXEC_BATCHED and not args.no_graph,
             "tile": None if tile is None else {"variant": tile[0], "extent": tile[1],
                                                "threads": tile[2],
                                                "xy_edges_in_one_sweep": tile[0] >= 8},

@@ -73,19 +73,25 @@ struct Kernels {
   // ghost layers filled before by fill_cf
   // lam_next (nullable, stage 3 only): accumulate the next step's CFL rate
   // over leaf cells not on coarse/fine faces (cfmask: per-pid face bits)
-  // ev0/ev1 (optional): events stamped at the dispatch's own start and end
+  // ev0/ev1 (optional): events stamped at the dispatch's own start and end.
+  // lam_in (stage 1 only, optional): take dt = CFL / *lam_in instead of *dt,
+  // write it to *dt_out and clear *lam_next (the slot stage 3 accumulates in)
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count,
                     const double* dt, bool fuse, unsigned long long* lam_next,
                     const uint8_t* cfmask, hipStream_t s, hipEvent_t ev0 = nullptr,
-                    hipEvent_t ev1 = nullptr);
+                    hipEvent_t ev1 = nullptr, const unsigned long long* lam_in = nullptr,
+                    double* dt_out = nullptr);
   static void reflux(const DevMesh& m, int mode, double* out, const double* fr,
                      const int* list, int count, const double* dt, double w,
                      unsigned long long* lam_next, hipStream_t s);
-  // reflux items and the finest level's restriction items in one launch
+  // refluxing and the restriction of the two finest levels in one launch:
+  // reflux items, level-lup patches with children (plist), level-lup leaves
+  // without coarse/fine faces (slist); lup = finest level - 1
   static void post(const DevMesh& m, int mode, double* out, const double* fr, const int* rlist,
-                   int nref, const int* slist, int nres, const double* dt, double w,
-                   unsigned long long* lam_next, hipStream_t s);
+                   int nref, const int* plist, int npair, const int* slist, int nsingle,
+                   int lup, const double* dt, double w, unsigned long long* lam_next,
+                   hipStream_t s);
   static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
                              hipStream_t s);
   static void max_rate(const DevMesh& m, const double* U, const int* list, int count,

@@ -94,6 +94,8 @@ struct amr_hierarchy {
   // host mirrors of the work lists
   std::vector<int> lists;
   amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfregions{}, cands{};
+  // post-stage restriction of the two finest levels (see Kernels::post)
+  amr::ListView post_pairs{}, post_singles{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
   std::vector<int> last_created;
   std::vector<uint8_t> h_active_leaf;
@@ -356,6 +358,20 @@ void sync_tables(amr_hierarchy* h, bool full) {
       ++nref;
     }
   }
+  // level-(L-2) patches with children, and level-(L-2) leaves (L-2 >= 1)
+  // without coarse/fine faces
+  const int lup = f.nlev - 2;
+  const int pp0 = begin_list();
+  for (int pid : order)
+    if (lup >= 0 && f.level[pid] == lup && !f.is_leaf(pid)) L.push_back(pid);
+  const int ps0 = begin_list();
+  {
+    std::vector<uint8_t> has_reflux(f.max_patches, 0);
+    for (int i = r0; i < r0 + 2 * nref; i += 2) has_reflux[L[i]] = 1;
+    for (int pid : order)
+      if (lup >= 1 && f.level[pid] == lup && f.is_leaf(pid) && !has_reflux[pid]) L.push_back(pid);
+  }
+  const int ps1 = begin_list();
   int rs[amr::kMaxLev + 1] = {};
   for (int l = 0; l < f.nlev; ++l) {
     rs[l] = begin_list();
@@ -390,6 +406,8 @@ void sync_tables(amr_hierarchy* h, bool full) {
   h->cands = {h->d_lists + k0, t0 - k0};
   h->tiles = {h->d_lists + t0, (r0 - t0) / 2};
   h->reflux = {h->d_lists + r0, nref};
+  h->post_pairs = {h->d_lists + pp0, ps0 - pp0};
+  h->post_singles = {h->d_lists + ps0, ps1 - ps0};
   for (int l = 0; l < f.nlev; ++l) {
     h->restr[l] = {h->d_lists + rs[l], rs[l + 1] - rs[l]};
     h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
@@ -443,8 +461,11 @@ void do_restrict(amr_hierarchy* h, int buf) {
     });
 }
 
+// lam_in (stage 1 of a step): dt comes from that rate slot and is written to
+// dt_out; lam_next is then the slot to clear, at stage 3 the slot to fill.
 void do_stage(amr_hierarchy* h, int stage, const double* dt,
-              unsigned long long* lam_next = nullptr) {
+              unsigned long long* lam_next = nullptr,
+              const unsigned long long* lam_in = nullptr, double* dt_out = nullptr) {
   static const int src[4] = {0, 0, 1, 2};
   static const int dst[4] = {0, 1, 2, 0};
   static const double w[4] = {0.0, 1.0, 0.25, 2.0 / 3.0};
@@ -456,17 +477,19 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
     hipEvent_t a = nullptr, b = nullptr;
     if (h->profiling) h->prof_pair(&a, &b, (long long)c * tcells);
     Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
-                   stage == 3 ? lam_next : nullptr, h->d_cfmask, h->stream, a, b);
+                   (stage == 3 || lam_in) ? lam_next : nullptr, h->d_cfmask, h->stream, a, b,
+                   lam_in, dt_out);
   });
   if (h->exec_mode == AMR_EXEC_BATCHED) {
-    // refluxing and the finest restriction share a launch; coarser levels
-    // follow, finest first
-    const int fl = h->forest.nlev - 1;
-    const amr::ListView rs = fl >= 1 ? h->restr[fl] : amr::ListView{};
-    Kernels::post(h->dm, stage, h->U[d], h->fr, h->reflux.ptr, h->reflux.count, rs.ptr, rs.count,
-                  dt, w[stage], stage == 3 ? lam_next : nullptr, h->stream);
+    // refluxing and the restriction of the two finest levels share a launch;
+    // coarser levels follow, finest first
+    const int lup = h->forest.nlev - 2;
+    Kernels::post(h->dm, stage, h->U[d], h->fr, h->reflux.ptr, h->reflux.count,
+                  h->post_pairs.ptr, h->post_pairs.count, h->post_singles.ptr,
+                  h->post_singles.count, lup, dt, w[stage], stage == 3 ? lam_next : nullptr,
+                  h->stream);
     h->check_launch();
-    for (int l = fl - 1; l >= 1; --l)
+    for (int l = lup - 1; l >= 1; --l)
       over_list(h, h->restr[l], 1, [&](const int* p, int c) {
         Kernels::restrict_level(h->dm, h->U[d], p, c, h->stream);
       });
@@ -497,9 +520,14 @@ void do_dt(amr_hierarchy* h, int buf, double* dt) {
 // one step: dt from the current rate slot, three stages; stage 3 and its
 // flux correction accumulate the rate of the new U^n into the other slot
 void do_step(amr_hierarchy* h, double* dt, int cur) {
-  Kernels::dt_from_rate(h->dm, h->d_lam + cur, dt, h->d_lam + (1 - cur), h->stream);
-  h->check_launch();
-  do_stage(h, 1, dt);
+  if (h->exec_mode == AMR_EXEC_BATCHED) {
+    // dt from the rate slot inside the stage-1 launch
+    do_stage(h, 1, dt, h->d_lam + (1 - cur), h->d_lam + cur, dt);
+  } else {
+    Kernels::dt_from_rate(h->dm, h->d_lam + cur, dt, h->d_lam + (1 - cur), h->stream);
+    h->check_launch();
+    do_stage(h, 1, dt);
+  }
   do_stage(h, 2, dt);
   do_stage(h, 3, dt, h->d_lam + (1 - cur));
 }
@@ -655,11 +683,11 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
       for (int l = 0; l < f.nlev; ++l) t += (long long)f.cap[l] * Kernels::tiles_per_patch(v, f.n[l]);
       tiles = std::max(tiles, t);
     }
-    // all, leaves, coarsening candidates, reflux (2), restriction, new
-    // patches: 7 per patch; ghost regions: 2 per region and patch; tiles: 2
-    // per tile
+    // all, leaves, coarsening candidates, reflux (2), post-stage pairs and
+    // singles, restriction, new patches: 9 per patch; ghost regions: 2 per
+    // region and patch; tiles: 2 per tile
     const long long regions = ipow(3, cfg->dim) - 1;
-    h->lists_cap = 2 * tiles + (7 + 2 * regions) * mp + 64;
+    h->lists_cap = 2 * tiles + (9 + 2 * regions) * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);

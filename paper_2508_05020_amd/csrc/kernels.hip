@@ -128,8 +128,7 @@ template <int D>
 __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __restrict__ fr,
                                              const double* __restrict__ frc, int l,
                                              const int pc[3], const int c[3], int f,
-                                             double coef, double* __restrict__ P,
-                                             long long vs) {
+                                             double coef, double u[D + 2]) {
   constexpr int NV = D + 2;
   const LevelC& L = m.lv[l];
   const LevelC& Fv = m.lv[l + 1];
@@ -192,7 +191,6 @@ __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __r
 #pragma unroll
     for (int v = 0; v < NV; ++v) sub[s][v] = frf[((j * 2 + fside) * NV + v) * nfface + ft];
   }
-  const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
   const double sgn = side ? 1.0 : -1.0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -202,7 +200,7 @@ __device__ __forceinline__ void face_correct(const DevMesh& m, const double* __r
     else avg = ((sub[0][v] + sub[1][v]) + (sub[2][v] + sub[3][v])) * 0.25;
     if (!ok) avg = __builtin_nan("");
     const double gc = frc[((j * 2 + side) * NV + v) * nface + t];
-    P[v * vs + off] = fma(coef, sgn * (gc - avg), P[v * vs + off]);
+    u[v] = fma(coef, sgn * (gc - avg), u[v]);
   }
 }
 
@@ -252,14 +250,16 @@ __device__ __forceinline__ void reflux_item(const DevMesh& m, int mode, double* 
     bool owned = true;
     for (int g = 0; g < f; ++g) owned &= !((mask & (1 << g)) && on_face(c, g));
     if (!owned) continue;
-    for (int g = f; g < 2 * D; ++g)
-      if ((mask & (1 << g)) && on_face(c, g))
-        face_correct<D>(m, fr, frc, l, pc, c, g, coef, P, vs);
-    if (want_rate) {
-      const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
-      double u[NV];
+    // the cell's values stay in registers through all of its corrections
+    const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+    double u[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
+    for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
+    for (int g = f; g < 2 * D; ++g)
+      if ((mask & (1 << g)) && on_face(c, g)) face_correct<D>(m, fr, frc, l, pc, c, g, coef, u);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[v * vs + off] = u[v];
+    if (want_rate) {
       const unsigned long long bits = cell_rate_bits<D>(u, m, L.h);
       best = bits > best ? bits : best;
     }
@@ -280,10 +280,9 @@ __global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __re
 // Restriction of one child patch into the covered cells of its parent:
 // pairwise sums in x, then y, then z order, times 2^-D.
 template <int D>
-__device__ __forceinline__ void restrict_item(const DevMesh& m, double* __restrict__ U,
-                                              const int* __restrict__ list, int item) {
+__device__ __forceinline__ void restrict_patch(const DevMesh& m, double* __restrict__ U,
+                                               int cpid) {
   constexpr int NV = D + 2;
-  const int cpid = list[item];
   const int lf = m.level[cpid];
   const int ppid = m.parent[cpid];
   const LevelC& F = m.lv[lf];
@@ -324,23 +323,47 @@ template <int D>
 __global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
                                                   const int* __restrict__ list, int count) {
   if ((int)blockIdx.x >= count) return;
-  restrict_item<D>(m, U, list, blockIdx.x);
+  restrict_patch<D>(m, U, list[blockIdx.x]);
 }
 
-// After a stage: refluxing and the restriction of the finest level in one
-// launch (blocks [0, nref) reflux, the rest restrict).  The two touch
-// disjoint cells: refluxing changes leaf cells below the finest level, the
-// finest restriction reads finest-level cells and writes non-leaf cells.
+// After a stage, in one launch: refluxing and the restriction of the two
+// finest levels, L-1 into L-2 and L-2 into L-3 (when L-2 >= 1).  Blocks:
+//  [0, nref)            reflux items (pid, mask); a level-(L-2) item then
+//                       restricts its (corrected) patch into its parent;
+//  [nref, +npair)       level-(L-2) patches with children: restrict every
+//                       child into the patch, then the patch into its parent;
+//  [.., +nsingle)       level-(L-2) leaves without coarse/fine faces:
+//                       restrict into the parent.
+// Each block's second restriction reads only what the same block wrote
+// (block barrier between); the blocks touch disjoint cells otherwise:
+// refluxing changes leaf cells, restriction writes non-leaf cells.
 template <int D, int NT>
 __global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode, double* __restrict__ out,
                                              const double* __restrict__ fr,
                                              const int* __restrict__ rlist, int nref,
-                                             const int* __restrict__ slist, int nres,
-                                             const double* __restrict__ dtp, double w,
+                                             const int* __restrict__ plist, int npair,
+                                             const int* __restrict__ slist, int nsingle,
+                                             int lup, const double* __restrict__ dtp, double w,
                                              unsigned long long* __restrict__ lam_next) {
   const int b = blockIdx.x;
-  if (b < nref) reflux_item<D, NT>(m, mode, out, fr, rlist, b, dtp, w, lam_next);
-  else if (b - nref < nres) restrict_item<D>(m, out, slist, b - nref);
+  if (b < nref) {
+    reflux_item<D, NT>(m, mode, out, fr, rlist, b, dtp, w, lam_next);
+    const int pid = rlist[2 * b];
+    if (lup >= 1 && m.level[pid] == lup) {
+      __syncthreads();
+      restrict_patch<D>(m, out, pid);
+    }
+  } else if (b - nref < npair) {
+    const int pid = plist[b - nref];
+    const int nc = m.nchild[pid];
+    for (int k = 0; k < nc; ++k) restrict_patch<D>(m, out, m.child[(long long)pid * m.maxc + k]);
+    if (lup >= 1) {
+      __syncthreads();
+      restrict_patch<D>(m, out, pid);
+    }
+  } else if (b - nref - npair < nsingle) {
+    restrict_patch<D>(m, out, slist[b - nref - npair]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -616,15 +639,20 @@ void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
 }
 
 void Kernels::post(const DevMesh& m, int mode, double* out, const double* fr,
-                   const int* rlist, int nref, const int* slist, int nres, const double* dt,
-                   double w, unsigned long long* lam_next, hipStream_t s) {
-  const int nb = nref + nres;
+                   const int* rlist, int nref, const int* plist, int npair, const int* slist,
+                   int nsingle, int lup, const double* dt, double w,
+                   unsigned long long* lam_next, hipStream_t s) {
+  const int nb = nref + npair + nsingle;
   if (nb <= 0) return;
+#define AMR_POST(D, NT)                                                                     \
+  k_post<D, NT><<<nb, NT, 0, s>>>(m, mode, out, fr, rlist, nref, plist, npair, slist, nsingle, \
+                                  lup, dt, w, lam_next)
   switch (m.dim) {
-    case 1: k_post<1, 64><<<nb, 64, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
-    case 2: k_post<2, 64><<<nb, 64, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
-    default: k_post<3, 256><<<nb, 256, 0, s>>>(m, mode, out, fr, rlist, nref, slist, nres, dt, w, lam_next); break;
+    case 1: AMR_POST(1, 64); break;
+    case 2: AMR_POST(2, 64); break;
+    default: AMR_POST(3, 256); break;
   }
+#undef AMR_POST
 }
 
 void Kernels::restrict_level(const DevMesh& m, double* U, const int* list, int count,

@@ -115,26 +115,40 @@ struct EdgeState {
   double p, T, u[D];
 };
 
-// Conserved state and direction-J flux of an edge state (Eq. (1)-(3), (5)-(7)).
+// Density, total energy and direction-J signal speed |u_J| + c of an edge
+// state (Eq. (5)-(7), T = p / rho).
 template <int D, int J>
-__device__ __forceinline__ void edge_flux(const DevMesh& m, const EdgeState<D>& w,
-                                          double U[D + 2], double F[D + 2], double& speed) {
-  const double rho = w.p * rcp_nr(w.T);
+__device__ __forceinline__ void edge_thermo(const DevMesh& m, const EdgeState<D>& w, double& rho,
+                                            double& E, double& speed) {
+  rho = w.p * rcp_nr(w.T);
   double uu = w.u[0] * w.u[0];
 #pragma unroll
   for (int i = 1; i < D; ++i) uu = fma(w.u[i], w.u[i], uu);
-  const double E = fma(0.5 * rho, uu, w.p * m.igm1);
-  U[0] = rho;
-  F[0] = rho * w.u[J];
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const double mi = rho * w.u[i];
-    U[1 + i] = mi;
-    F[1 + i] = (i == J) ? fma(mi, w.u[J], w.p) : mi * w.u[J];
-  }
-  U[D + 1] = E;
-  F[D + 1] = (E + w.p) * w.u[J];
+  E = fma(0.5 * rho, uu, w.p * m.igm1);
   speed = sqrt_nr(m.gamma * w.T) + fabs(w.u[J]);
+}
+
+// Variable v of the conserved state and of the direction-J flux of an edge
+// state (Eq. (1)-(3)).
+template <int D, int J>
+__device__ __forceinline__ void edge_uf(const EdgeState<D>& w, double rho, double E, int v,
+                                        double& U, double& F) {
+  if (v == 0) {
+    U = rho;
+    F = rho * w.u[J];
+  } else if (v == D + 1) {
+    U = E;
+    F = (E + w.p) * w.u[J];
+  } else {
+    const int i = v - 1;
+    double ui = w.u[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k)
+      if (k == i) ui = w.u[k];
+    const double mi = rho * ui;
+    U = mi;
+    F = (i == J) ? fma(mi, w.u[J], w.p) : mi * w.u[J];
+  }
 }
 
 template <int D, int TX, int TY, int TZ>
@@ -268,44 +282,66 @@ __device__ __forceinline__ void load_union(const DevMesh& m, const double* __res
 // Riemann flux of direction J at one edge whose window (nodes i-2 .. i+3)
 // starts at layout index `base` of the primitives in LDS (NEXT nodes per
 // primitive, STEP between neighbours along J); stored doubled at sF[v NED + e].
-template <int D, int J, int NEXT, int STEP, int NED>
-__device__ __forceinline__ void edge_at(const DevMesh& m, const double* sP, int base, double* sF,
-                                        int e) {
+template <int D, int J, int NEXT, int STEP, int NED, bool CENTRAL>
+__device__ __forceinline__ void edge_at_scheme(const DevMesh& m, const double* sP, int base,
+                                               double* sF, int e) {
   constexpr int NV = D + 2;
-  constexpr int NQ = D + 2;  // interpolated primitives: p, T, u_j
-  EdgeState<D> wl, wr;
-  double lo[NQ], hi[NQ], lv[NQ], rv[NQ];
   const double eps4 = 4.0 * m.eps;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  // interpolated left/right values of primitive q (p, T, u_j) at this edge
+  auto interp = [&](int q, double& l, double& r) {
     const double* col = sP + q * NEXT + base;
     const double v0 = col[0], v1 = col[STEP], v2 = col[2 * STEP];
     const double v3 = col[3 * STEP], v4 = col[4 * STEP], v5 = col[5 * STEP];
-    if (m.scheme == AMR_SCHEME_CENTRAL) {
-      lv[q] = central4(v1, v2, v3, v4);
-      rv[q] = lv[q];
+    if constexpr (CENTRAL) {
+      l = central4(v1, v2, v3, v4);
+      r = l;
     } else {
-      weno5_pair(v0, v1, v2, v3, v4, v5, eps4, lv[q], rv[q]);
+      weno5_pair(v0, v1, v2, v3, v4, v5, eps4, l, r);
     }
-    lo[q] = v2;
-    hi[q] = v3;
-  }
-  const bool ok = (lv[0] > 0.0) && (lv[1] > 0.0) && (rv[0] > 0.0) && (rv[1] > 0.0);
-  wl.p = ok ? lv[0] : lo[0];
-  wl.T = ok ? lv[1] : lo[1];
-  wr.p = ok ? rv[0] : hi[0];
-  wr.T = ok ? rv[1] : hi[1];
+  };
+  // p and T first: their signs decide the first-order fallback, which is
+  // then applied to each velocity component as soon as it is interpolated
+  // (fewer values live at once)
+  EdgeState<D> wl, wr;
+  double lp, rp, lT, rT;
+  interp(0, lp, rp);
+  interp(1, lT, rT);
+  const bool ok = (lp > 0.0) && (lT > 0.0) && (rp > 0.0) && (rT > 0.0);
+  const double* c2 = sP + base + 2 * STEP;
+  wl.p = ok ? lp : c2[0];
+  wr.p = ok ? rp : c2[STEP];
+  wl.T = ok ? lT : c2[NEXT];
+  wr.T = ok ? rT : c2[NEXT + STEP];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    wl.u[i] = ok ? lv[2 + i] : lo[2 + i];
-    wr.u[i] = ok ? rv[2 + i] : hi[2 + i];
+    double lu, ru;
+    interp(2 + i, lu, ru);
+    wl.u[i] = ok ? lu : c2[(2 + i) * NEXT];
+    wr.u[i] = ok ? ru : c2[(2 + i) * NEXT + STEP];
   }
-  double UL[NV], FL[NV], UR[NV], FR[NV], sl, sr;
-  edge_flux<D, J>(m, wl, UL, FL, sl);
-  edge_flux<D, J>(m, wr, UR, FR, sr);
+  // Rusanov flux (Eq. (11)-(12)), stored doubled, one variable at a time
+  double rl, El, sl, rr, Er, sr;
+  edge_thermo<D, J>(m, wl, rl, El, sl);
+  edge_thermo<D, J>(m, wr, rr, Er, sr);
   const double S = fmax(sr, sl);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UR[v] - UL[v], FR[v] + FL[v]);
+  for (int v = 0; v < NV; ++v) {
+    double UL, FL, UR, FR;
+    edge_uf<D, J>(wl, rl, El, v, UL, FL);
+    edge_uf<D, J>(wr, rr, Er, v, UR, FR);
+    sF[v * NED + e] = fma(-S, UR - UL, FR + FL);
+  }
+}
+
+// The scheme branch taken once per edge, so that each path is straight-line
+// code the compiler can schedule across the primitives.
+template <int D, int J, int NEXT, int STEP, int NED>
+__device__ __forceinline__ void edge_at(const DevMesh& m, const double* sP, int base, double* sF,
+                                        int e) {
+  if (m.scheme == AMR_SCHEME_CENTRAL)
+    edge_at_scheme<D, J, NEXT, STEP, NED, true>(m, sP, base, sF, e);
+  else
+    edge_at_scheme<D, J, NEXT, STEP, NED, false>(m, sP, base, sF, e);
 }
 
 // Face fluxes G of direction J (flux form of Eq. (9)) from the edge fluxes
@@ -456,7 +492,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 :
                                               const int* __restrict__ tiles, int count,
                                               const double* __restrict__ dtp,
                                               unsigned long long* __restrict__ lam_next,
-                                              const uint8_t* __restrict__ cfmask) {
+                                              const uint8_t* __restrict__ cfmask,
+                                              const unsigned long long* __restrict__ lam_in,
+                                              double* __restrict__ dt_out) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
@@ -509,7 +547,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 :
   }
 
   const long long vs = var_stride<D>(full);
-  const double dt = (mode == kModeRHS) ? 0.0 : dtp[0];
+  // stage 1 of a step may take dt = CFL / rate from the rate slot itself
+  // (every block computes it; the first work item publishes it for the rest
+  // of the step and clears the slot stage 3 accumulates into)
+  double dt;
+  if (mode == kModeRHS) {
+    dt = 0.0;
+  } else if (lam_in) {
+    dt = m.cfl / __longlong_as_double((long long)lam_in[0]);
+    if (item == 0 && threadIdx.x == 0) {
+      dt_out[0] = dt;
+      lam_next[0] = 0ull;
+    }
+  } else {
+    dt = dtp[0];
+  }
   constexpr double c23 = 2.0 / 3.0;
   // next step's CFL rate from the final leaf values; cells on coarse/fine
   // faces are left to the flux-correction kernel, which changes them
@@ -596,7 +648,8 @@ int Kernels::tiles_per_patch(int v, int n) {
 void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count, const double* dt,
                     bool fuse, unsigned long long* lam_next, const uint8_t* cfmask,
-                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                    const unsigned long long* lam_in, double* dt_out) {
   if (count <= 0) return;
   // one block per work item, rounded up to whole groups of kXcds blocks (see
   // xcd_item)
@@ -606,10 +659,11 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
     if (ev0)                                                                                 \
       hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, ev0, \
                             ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,   \
-                            cfmask);                                                         \
+                            cfmask, lam_in, dt_out);                                         \
     else                                                                                     \
       hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, m,     \
-                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask);        \
+                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask, lam_in, \
+                         dt_out);                                                            \
   } while (0)
 #define AMR_STAGE(D, TX, TY, TZ, NT, B)        \
   do {                                         \
