@@ -486,7 +486,7 @@ __device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict_
 }
 
 template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 : 1))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 : 7))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
                                               const int* __restrict__ tiles, int count,
