@@ -100,8 +100,10 @@ struct Kernels {
   // dt = cfl / rate; also zeroes *clear (nullable), the next rate accumulator
   static void dt_from_rate(const DevMesh& m, const unsigned long long* lam_bits,
                            double* dt, unsigned long long* clear, hipStream_t s);
+  // fuse: halo cells read from same-level neighbours directly; ghost layers
+  // hold only the prolonged cells (filled by fill_cf beforehand)
   static void tag(const DevMesh& m, const double* U, const int* list, int count,
-                  uint8_t* has_tag, uint8_t* raw, hipStream_t s);
+                  uint8_t* has_tag, uint8_t* raw, bool fuse, hipStream_t s);
   static void cell_tags(const DevMesh& m, const uint8_t* raw, const int* list, int count,
                         uint8_t* out, hipStream_t s);
   static void requests(const DevMesh& m, const uint8_t* has_tag, const uint8_t* active_leaf,

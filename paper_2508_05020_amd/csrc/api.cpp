@@ -98,6 +98,7 @@ struct amr_hierarchy {
   amr::ListView post_pairs{}, post_singles{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
   std::vector<int> last_created;
+  std::vector<int8_t> parent_interior;  // scratch of sync_tables
   std::vector<uint8_t> h_active_leaf;
   long long leaf_cells = 0;
 
@@ -300,8 +301,29 @@ void sync_tables(amr_hierarchy* h, bool full) {
   // through a non-periodic boundary set to 0 (those ghosts copy the nearest
   // interior cell), points at a missing same-level patch
   const int c0 = begin_list();
+  // a leaf whose parent's Moore neighbours all have children has every
+  // same-level neighbour (children come in complete sets): nothing to check
+  std::vector<int8_t>& pint = h->parent_interior;
+  pint.assign(mp, -1);
+  auto parent_interior = [&](int P) {
+    if (pint[P] < 0) {
+      const int lp = f.level[P];
+      const int cp[3] = {f.coord[3 * P], f.coord[3 * P + 1], f.coord[3 * P + 2]};
+      int8_t ok = 1;
+      for (const auto& off : f.moore()) {
+        const int q = f.neighbour(lp, cp, off[0], off[1], off[2]);
+        if (q == -1 || (q >= 0 && f.is_leaf(q))) {
+          ok = 0;
+          break;
+        }
+      }
+      pint[P] = ok;
+    }
+    return pint[P] == 1;
+  };
   for (int pid : order) {
     if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
+    if (parent_interior(f.parent[pid])) continue;
     const int l = f.level[pid];
     const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
     for (const auto& off : f.moore()) {
@@ -312,8 +334,7 @@ void sync_tables(amr_hierarchy* h, bool full) {
         if ((v < 0 || v >= f.np[l]) && !f.periodic[j]) src[j] = 0;
         self &= src[j] == 0;
       }
-      int q[3];
-      if (self || !f.shifted(l, c, src, q) || f.lookup(l, q) >= 0) continue;
+      if (self || f.neighbour(l, c, src[0], src[1], src[2]) != -1) continue;
       L.push_back(pid);
       L.push_back((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
     }
@@ -346,10 +367,8 @@ void sync_tables(amr_hierarchy* h, bool full) {
     int mask = 0;
     for (int j = 0; j < f.dim; ++j)
       for (int side = 0; side < 2; ++side) {
-        int off[3] = {0, 0, 0}, q[3];
-        off[j] = side ? 1 : -1;
-        if (!f.shifted(l, c, off, q)) continue;
-        const int qp = f.lookup(l, q);
+        const int o = side ? 1 : -1;
+        const int qp = f.neighbour(l, c, j == 0 ? o : 0, j == 1 ? o : 0, j == 2 ? o : 0);
         if (qp >= 0 && !f.is_leaf(qp)) mask |= 1 << (2 * j + side);
       }
     if (mask) {
@@ -535,13 +554,24 @@ void do_step(amr_hierarchy* h, double* dt, int cur) {
 // Tags of every leaf and of every coarsening candidate (on its restricted
 // data), then the requests.
 void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_t* cells) {
-  do_fill(h, buf, h->leaves);
-  do_fill(h, buf, h->cands);
+  // ghosts: with the fused halo only the prolonged ones (coarsening
+  // candidates have children, hence every same-level neighbour, and need
+  // none); else full fills
+  const bool fuse = h->fuse_halo;
+  if (fuse) {
+    over_list(h, h->cfregions, 2, [&](const int* p, int c) {
+      Kernels::fill_cf(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+    });
+  } else {
+    do_fill(h, buf, h->leaves);
+    do_fill(h, buf, h->cands);
+  }
   over_list(h, h->leaves, 1, [&](const int* p, int c) {
-    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, cells ? h->d_raw : nullptr, h->stream);
+    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, cells ? h->d_raw : nullptr, fuse,
+                 h->stream);
   });
   over_list(h, h->cands, 1, [&](const int* p, int c) {
-    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, nullptr, h->stream);
+    Kernels::tag(h->dm, h->U[buf], p, c, h->d_has_tag, nullptr, fuse, h->stream);
   });
   if (cells)
     over_list(h, h->leaves, 1, [&](const int* p, int c) {

@@ -102,12 +102,6 @@ void Forest::init(const amr_config& cfg) {
       }
 }
 
-int Forest::map_index(int l, const int c[3]) const {
-  int idx = c[0];
-  if (dim >= 2) idx += np[l] * c[1];
-  if (dim >= 3) idx += np[l] * np[l] * c[2];
-  return map_off[l] + idx;
-}
 
 bool Forest::shifted(int l, const int c[3], const int off[3], int out[3]) const {
   out[0] = out[1] = out[2] = 0;
@@ -337,10 +331,28 @@ int Forest::count_leaves() const {
 
 std::vector<int> Forest::sorted_active() const {
   std::vector<int> out;
+  // (level, z, y, x, pid) packed into one 64-bit key when the fields fit
+  // (level < 16, coordinates < 2^14, pid < 2^17), else the comparator
+  bool packed = max_patches <= (1 << 17);
+  for (int l = 0; l < nlev; ++l) packed &= np[l] <= (1 << 14);
+  if (packed) {
+    std::vector<uint64_t> keys;
+    for (int pid = 0; pid < max_patches; ++pid) {
+      if (!active[pid]) continue;
+      keys.push_back(((uint64_t)level[pid] << 59) | ((uint64_t)coord[3 * pid + 2] << 45) |
+                     ((uint64_t)coord[3 * pid + 1] << 31) | ((uint64_t)coord[3 * pid] << 17) |
+                     (uint64_t)pid);
+    }
+    std::sort(keys.begin(), keys.end());
+    out.reserve(keys.size());
+    for (uint64_t k : keys) out.push_back((int)(k & ((1u << 17) - 1)));
+    return out;
+  }
   for (int pid = 0; pid < max_patches; ++pid)
     if (active[pid]) out.push_back(pid);
   std::sort(out.begin(), out.end(), [&](int a, int b) { return order_less(*this, a, b); });
   return out;
 }
+
 
 }  // namespace amr

@@ -41,7 +41,12 @@ class Forest {
   std::vector<int> map_dirty;
   std::vector<int> touched;
 
-  int map_index(int l, const int c[3]) const;
+  int map_index(int l, const int c[3]) const {
+    int idx = c[0];
+    if (dim >= 2) idx += np[l] * c[1];
+    if (dim >= 3) idx += np[l] * np[l] * c[2];
+    return map_off[l] + idx;
+  }
   int lookup(int l, const int c[3]) const { return map[map_index(l, c)]; }
   bool is_leaf(int pid) const { return nchild[pid] == 0; }
   int levels_in_use() const;
@@ -50,6 +55,22 @@ class Forest {
 
   // Same-level position c + off; false outside a non-periodic domain.
   bool shifted(int l, const int c[3], const int off[3], int out[3]) const;
+  // pid of the same-level patch at c + (o0, o1, o2), offsets in {-1, 0, 1}:
+  // -1 when absent, -2 outside a non-periodic domain.
+  int neighbour(int l, const int c[3], int o0, int o1, int o2) const {
+    const int n = np[l];
+    const int o[3] = {o0, o1, o2};
+    int q[3] = {0, 0, 0};
+    for (int j = 0; j < dim; ++j) {
+      int v = c[j] + o[j];
+      if (v < 0 || v >= n) {
+        if (!periodic[j]) return -2;
+        v += v < 0 ? n : -n;
+      }
+      q[j] = v;
+    }
+    return map[map_index(l, q)];
+  }
   // Level l-1 position whose region contains level-l position c.
   void covering(int l, const int c[3], int out[3]) const;
   // Moore offsets, (dz, dy, dx) lexicographic with dx fastest.

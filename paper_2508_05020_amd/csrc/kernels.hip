@@ -424,7 +424,44 @@ __device__ __forceinline__ void rho_p_at(const DevMesh& m, const double* P, long
   p = pressure_exact<D>(u, m.gm1);
 }
 
-template <int D>
+// rho and p at patch-local cell c of patch P (level l, patch position pc);
+// with FUSE a cell outside the patch is read from the same-level patch that
+// holds it (neighbour table sN by offset code, periodic wrap and transmissive
+// clamp applied), else from P's own ghost layer (prolonged values).
+template <int D, bool FUSE>
+__device__ __forceinline__ void rho_p_node(const DevMesh& m, const double* __restrict__ U,
+                                           const double* __restrict__ P, long long vs, int full,
+                                           int n, int l, const int pc[3], const int* sN,
+                                           const int c[3], double& rho, double& p) {
+  if constexpr (FUSE) {
+    bool inside = true;
+    for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
+    if (!inside) {
+      const LevelC& L = m.lv[l];
+      int code = 0, loc[3] = {0, 0, 0}, mul = 1;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int g = bc_map(pc[j] * n + c[j], L.cells, m.periodic[j]);
+        const int q = g / n;
+        int o = q - pc[j];
+        if (o > 1) o -= L.np;
+        if (o < -1) o += L.np;
+        loc[j] = g - q * n;
+        code += (o + 1) * mul;
+        mul *= 3;
+      }
+      const int src = sN[code];
+      if (src >= 0) {
+        rho_p_at<D>(m, U + patch_base(m, src, l), vs,
+                    box_off<D>(full, loc[0] + NG, loc[1] + NG, loc[2] + NG), rho, p);
+        return;
+      }
+    }
+  }
+  rho_p_at<D>(m, P, vs, box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG), rho, p);
+}
+
+template <int D, bool FUSE>
 __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict__ U,
                                              const int* __restrict__ list, int count,
                                              uint8_t* __restrict__ has_tag,
@@ -436,6 +473,28 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
   const int n = L.n, b = m.tag_buffer, w = n + 2 * b;
   const double* P = U + patch_base(m, pid, l);
   const long long vs = var_stride<D>(L.full);
+  const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  // same-level neighbours by offset code (o0+1) + 3 (o1+1) + 9 (o2+1)
+  __shared__ int sN[27];
+  if constexpr (FUSE) {
+    constexpr int NO = D == 1 ? 3 : (D == 2 ? 9 : 27);
+    const int t = threadIdx.x;
+    if (t < NO) {
+      int q[3] = {0, 0, 0};
+      bool in = true;
+      for (int j = 0; j < D; ++j) {
+        const int o = (j == 0 ? t : (j == 1 ? t / 3 : t / 9)) % 3 - 1;
+        int v = pc[j] + o;
+        if (v < 0 || v >= L.np) {
+          if (m.periodic[j]) v = (v + L.np) % L.np;
+          else in = false;
+        }
+        q[j] = v;
+      }
+      sN[t] = in ? map_at<D>(m, l, q) : -1;
+    }
+    __syncthreads();
+  }
   int total = w;
   if constexpr (D >= 2) total *= w;
   if constexpr (D >= 3) total *= w;
@@ -451,8 +510,8 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
       cp[j] += 1;
       cm[j] -= 1;
       double rp_, pp_, rm_, pm_;
-      rho_p_at<D>(m, P, vs, box_off<D>(L.full, cp[0] + NG, cp[1] + NG, cp[2] + NG), rp_, pp_);
-      rho_p_at<D>(m, P, vs, box_off<D>(L.full, cm[0] + NG, cm[1] + NG, cm[2] + NG), rm_, pm_);
+      rho_p_node<D, FUSE>(m, U, P, vs, L.full, n, l, pc, sN, cp, rp_, pp_);
+      rho_p_node<D, FUSE>(m, U, P, vs, L.full, n, l, pc, sN, cm, rm_, pm_);
       t |= fabs(rp_ - rm_) > m.theta * (fabs(rp_) + fabs(rm_));
       t |= fabs(pp_ - pm_) > m.theta * (fabs(pp_) + fabs(pm_));
     }
@@ -679,9 +738,17 @@ void Kernels::dt_from_rate(const DevMesh& m, const unsigned long long* lam, doub
 }
 
 void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,
-                  uint8_t* has_tag, uint8_t* raw, hipStream_t s) {
+                  uint8_t* has_tag, uint8_t* raw, bool fuse, hipStream_t s) {
   if (count <= 0) return;
-  AMR_DISPATCH_DIM(m.dim, k_tag, dim3(count), dim3(256), s, m, U, list, count, has_tag, raw);
+#define AMR_TAG(D)                                                                           \
+  do {                                                                                       \
+    if (fuse) k_tag<D, true><<<count, 256, 0, s>>>(m, U, list, count, has_tag, raw);          \
+    else k_tag<D, false><<<count, 256, 0, s>>>(m, U, list, count, has_tag, raw);              \
+  } while (0)
+  if (m.dim == 1) AMR_TAG(1);
+  else if (m.dim == 2) AMR_TAG(2);
+  else AMR_TAG(3);
+#undef AMR_TAG
 }
 
 void Kernels::cell_tags(const DevMesh& m, const uint8_t* raw, const int* list, int count,
