@@ -204,8 +204,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="launch every kernel of a step eagerly instead of replaying a hipGraph")
+    ap.add_argument("--step-graph", choices=["auto", "on", "off"], default="auto",
+                    help="replay each step as a hipGraph, launch eagerly, or time both "
+                         "(16 steps each, regrids included, after the warm-up) and keep the "
+                         "faster")
     ap.add_argument("--tile", type=int, default=None,
                     help="use this stage-kernel tile variant instead of autotuning")
     ap.add_argument("--learned", action="store_true",
@@ -241,8 +243,6 @@ def main() -> int:
     amr.init_from_ic(h, workloads.initial_data(cfg, args.seed))
     log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
         f"{h.leaf_cells()} leaf cells")
-    if args.no_graph:
-        h.set_graph(False)
     tile = None
     if args.tile is not None:
         h.set_tile_variant(args.tile)
@@ -272,6 +272,20 @@ def main() -> int:
     advance(args.warmup, False)
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} steps)")
+    use_graph = args.step_graph == "on"
+    if mode == amr.EXEC_BATCHED and args.step_graph == "auto":
+        per = {}
+        for g in (False, True):
+            h.set_graph(g)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            advance(16, False)
+            torch.cuda.synchronize()
+            per[g] = (time.perf_counter() - t0) / 16
+        use_graph = per[True] < per[False]
+        log(f"[bench] step graph {per[True] * 1e6:.0f} us, eager {per[False] * 1e6:.0f} us: "
+            f"{'graph' if use_graph else 'eager'}")
+    h.set_graph(use_graph and mode == amr.EXEC_BATCHED)
     # pass 1: whole-job throughput (step graphs replayed, no instrumentation)
     t0 = time.perf_counter()
     cells = advance(args.steps, True)
@@ -322,7 +336,7 @@ def main() -> int:
                         f"{'periodic' if all(cfg.periodic) else 'mixed bc'}, ic {cfg.ic} "
                         f"seed {args.seed}, CFL {cfg.cfl}, regrid every {cfg.regrid_interval}",
             "exec": args.exec_mode,
-            "step_graph": mode == amr.EXEC_BATCHED and not args.no_graph,
+            "step_graph": bool(use_graph and mode == amr.EXEC_BATCHED),
             "tile": None if tile is None else {"variant": tile[0], "extent": tile[1],
                                                "threads": tile[2],
                                                "xy_edges_in_one_sweep": tile[0] >= 8},

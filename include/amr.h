@@ -270,9 +270,13 @@ amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_d
 amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const uint16_t* b_dev,
                                  float* d_dev);
 
-/* hipGraph replay of amr_step in batched mode (default on): the kernels of
- * one step are captured once and replayed until the next regrid or mode
- * change; the graph holds kernel nodes only.  Results are identical. */
+/* hipGraph replay of amr_step in batched mode (default off): the kernels of
+ * one step are captured once and replayed until the next regrid that changes
+ * the mesh, or a mode change; the graph holds kernel nodes only.  Results are
+ * identical.  Off by default because a step is a few launches of several
+ * microseconds each, whose CPU launch cost eager launching already hides;
+ * callers that cannot afford the CPU time per step (or capture the step into
+ * their own graphs) turn it on. */
 amr_status amr_set_graph(amr_hierarchy* h, int enable);
 
 /* Tile variants of the fused stage kernel (cells per tile and block size):

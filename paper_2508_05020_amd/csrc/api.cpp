@@ -51,7 +51,7 @@ struct amr_hierarchy {
   bool fuse_halo = true;  // stage kernel gathers halos itself (no fill pass)
   // hipGraphs of one batched step (dt + 3 stages), one per parity of the CFL
   // rate double buffer, valid until the next regrid or mode change
-  bool use_graph = true;
+  bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t step_exec[2] = {nullptr, nullptr};
   const double* step_exec_dt[2] = {nullptr, nullptr};

@@ -322,6 +322,7 @@ def test_graph_replays_equal_eager_bitwise(name, amr):
     between, gives the eager result bit for bit."""
     o, hg, pg, _ = _pair(name, amr)
     _, he, pe, _ = _pair(name, amr)
+    hg.set_graph(True)
     he.set_graph(False)
     d = o.cfg.dim
     for s in range(1, 7):
