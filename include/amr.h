@@ -153,14 +153,19 @@ amr_status amr_compute_dt(amr_hierarchy* h, int buf, double* dt_dev);
  * restriction of every non-leaf patch.  dt is read from the device scalar. */
 amr_status amr_rk_stage(amr_hierarchy* h, int stage, const double* dt_dev);
 
-/* dt (into *dt_dev) followed by the three stages (async). */
+/* dt (into *dt_dev) followed by the three stages (async).  In batched mode
+ * dt is computed inside the first stage's launch from the CFL rate the
+ * previous step's last stage accumulated (or a fresh one after a regrid). */
 amr_status amr_step(amr_hierarchy* h, double* dt_dev);
 
-/* Gradient tagging of buffer `buf` (async; ghosts are filled first).
+/* Gradient tagging of buffer `buf` (async; halo cells come from the
+ * same-level neighbours, or from ghost layers filled first when the fused halo
+ * is off; prolonged ghost cells are always filled first).
  * Per pid (max_patches entries each): refine_req = leaf below the finest
  * level with a tagged cell within tag_buffer cells of its interior;
- * coarsen_req = patch whose children are all leaves without tags
- * (the requests of Fig. grid-meta).  cell_tags_dev (nullable) receives the
+ * coarsen_req = patch whose children are all leaves without tags and whose
+ * own (restricted) data carry no tag either (the requests of Fig.
+ * grid-meta; the tag criterion itself is not given in the paper).  cell_tags_dev (nullable) receives the
  * dilated per-cell tag of every leaf interior cell, one byte per cell in a
  * layout of (n_l + 8)^dim bytes per patch at offset amr_patch_offset/nvar. */
 amr_status amr_tag(amr_hierarchy* h, int buf, uint8_t* refine_req_dev,
@@ -202,10 +207,12 @@ amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq
  * mesh (no device work): the cells one step advances. */
 amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells);
 
-/* Timing of the fused RHS + stage kernel: while enabled, every launch of it is
- * bracketed by HIP events on the hierarchy's stream.  amr_profile (sync)
- * enables/disables and resets; amr_profile_read (sync) returns the summed
- * event time in ms, the number of launches and the leaf cells they covered. */
+/* Timing of the fused RHS + stage kernel: while enabled, every launch of it
+ * carries a pair of HIP events that the dispatch itself stamps at its start
+ * and end (extended launch), and amr_step launches eagerly.  amr_profile
+ * (sync) enables/disables and resets; amr_profile_read (sync) returns the
+ * summed event time in ms, the number of launches and the leaf cells they
+ * covered. */
 amr_status amr_profile(amr_hierarchy* h, int enable);
 amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, int64_t* cells);
 

@@ -609,7 +609,7 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
     if (ndeleted) *ndeleted = 0;
     return AMR_OK;
   }
-  const std::string why = h->forest.validate();
+  const std::string why = h->forest.validate_change(created);
   if (!why.empty()) {
     h->err = why;
     return AMR_E_MESH;
@@ -1186,7 +1186,11 @@ amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq
       }
       std::vector<int> created, deleted;
       f.regrid(rq.data(), cq.data(), created, deleted);
-      if (!f.validate().empty()) return AMR_E_MESH;
+      // the full check, and the local one the hierarchy runs after a regrid,
+      // which must agree with it
+      const bool ok_full = f.validate().empty();
+      const bool ok_local = f.validate_change(created).empty();
+      if (!ok_full || !ok_local) return AMR_E_MESH;
     }
     const std::vector<int> order = f.sorted_active();
     *n = (int)order.size();

@@ -271,10 +271,66 @@ void Forest::regrid(const uint8_t* refine_req, const uint8_t* coarsen_req,
     if (level[a] != level[b]) return level[a] > level[b];
     return order_less(*this, a, b);
   });
+  coarsened_.clear();
   for (int pid : cq) {
     if (!active[pid] || fresh_parent[pid]) continue;
-    if (coarsening_allowed(pid)) delete_children(pid, deleted);
+    if (coarsening_allowed(pid)) {
+      delete_children(pid, deleted);
+      coarsened_.push_back(pid);
+    }
   }
+}
+
+std::string Forest::validate_change(const std::vector<int>& created) const {
+  // R2 can only fail at patches with children near the change: the parents
+  // of created patches (and the patches Algorithm 1 refined around them,
+  // which are parents of created patches too), and patches one level below a
+  // coarsened patch that border its former children.
+  auto r2 = [&](int q) -> bool {
+    const int l = level[q];
+    const int c[3] = {coord[3 * q], coord[3 * q + 1], coord[3 * q + 2]};
+    for (const auto& off : moore_)
+      if (neighbour(l, c, off[0], off[1], off[2]) == -1) return false;
+    return true;
+  };
+  for (int q : created) {
+    const int l = level[q];
+    const int c[3] = {coord[3 * q], coord[3 * q + 1], coord[3 * q + 2]};
+    if (!active[q] || lookup(l, c) != q) return "patch map disagrees with the patch table";
+    int r[3];
+    covering(l, c, r);
+    if (lookup(l - 1, r) != parent[q]) return "parent link broken";
+    if (!r2(parent[q])) return "R2: a refined patch has an absent Moore neighbour";
+  }
+  for (int p : coarsened_) {
+    const int l = level[p] + 1;
+    if (l >= nlev) continue;
+    // former children's region on level l, grown by one patch
+    const int r = ratio[level[p]];
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int j = 0; j < dim; ++j) {
+      lo[j] = coord[3 * p + j] * r - 1;
+      hi[j] = coord[3 * p + j] * r + r;
+    }
+    for (int z = lo[2]; z <= (dim >= 3 ? hi[2] : lo[2]); ++z)
+      for (int y = lo[1]; y <= (dim >= 2 ? hi[1] : lo[1]); ++y)
+        for (int x = lo[0]; x <= hi[0]; ++x) {
+          int q3[3] = {x, y, z};
+          bool in = true;
+          for (int j = 0; j < dim; ++j) {
+            int& v = q3[j];
+            if (v < 0 || v >= np[l]) {
+              if (!periodic[j]) in = false;
+              else v = (v % np[l] + np[l]) % np[l];
+            }
+          }
+          if (!in) continue;
+          const int q = lookup(l, q3);
+          if (q >= 0 && !is_leaf(q) && !r2(q))
+            return "R2: a patch with children borders a coarsened region";
+        }
+  }
+  return "";
 }
 
 std::string Forest::validate() const {

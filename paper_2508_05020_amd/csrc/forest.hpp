@@ -88,6 +88,9 @@ class Forest {
 
   // Empty string when R1, R2 and the tree links hold.
   std::string validate() const;
+  // The same checks restricted to what the last regrid can have changed
+  // (its created patches and coarsened parents).
+  std::string validate_change(const std::vector<int>& created) const;
 
   // Active pids sorted by (level, z, y, x).
   std::vector<int> sorted_active() const;
@@ -96,6 +99,7 @@ class Forest {
   int alloc(int l, const int c[3], int par);
   void release(int pid);
   std::vector<std::set<int>> free_;
+  std::vector<int> coarsened_;  // patches whose children the last regrid deleted
   std::vector<std::array<int, 3>> moore_;
 };
 
