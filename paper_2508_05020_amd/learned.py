@@ -214,8 +214,9 @@ def learned_regrid(h: A.Hierarchy, pred: A.Predictor, tau: float, rounds: int = 
     for r in range(rounds):
         pr, pc = pred.predict(0, tau)
         tr, tc, _ = h.tag(0)
-        ref = (pr | tr).cpu().numpy()
-        coa = (pc & tc).cpu().numpy() if r == 0 else np.zeros_like(ref)
+        # combined on the host: the flags come back for the host regrid anyway
+        ref = pr.cpu().numpy() | tr.cpu().numpy()
+        coa = (pc.cpu().numpy() & tc.cpu().numpy()) if r == 0 else np.zeros_like(ref)
         if not ref.any() and not coa.any():
             break
         nc, nd = h.regrid(ref, coa)
