@@ -226,27 +226,37 @@ amr_status amr_judge(amr_hierarchy* h, int* uncovered);
 amr_status amr_set_exec_mode(amr_hierarchy* h, int mode);
 
 /* ------------------------------------------------------------------------
- * Learned refinement predictor (2D; not part of the paper).  A per-patch
+ * Learned refinement predictor (2D and 3D; not part of the paper).  A
  * convolutional network forecasts which cells the gradient tagger will tag
  * within the next steps, so that regridding can run less often; the plain
- * tagger remains the judge.  Input: normalised (rho, u, v, p) of an n x n
- * patch plus 3 halo cells, BF16, pixel-major with 4 channels innermost
- * ([npatch][(n+6)^2][4]).  Network: three valid 3x3 convolutions 4 -> 16 ->
- * 16 -> 1, bias, ReLU after the first two; BF16 weights and activations,
- * FP32 accumulation (MFMA); output logits [npatch][n^2] (FP32).
- * Parameters (FP32 master, 3057 floats): W1 [16][4][3][3], b1 [16],
- * W2 [16][16][3][3], b2 [16], W3 [16][3][3], b3.  Training: weighted binary
- * cross-entropy with logits averaged over cells, gradients reduced over
- * patches in a fixed order, Adam (beta 0.9 / 0.999, eps 1e-8) on the master
- * weights followed by a round-to-nearest-even BF16 copy.
+ * tagger remains the judge.  BF16 weights and activations, FP32 accumulation
+ * (MFMA).  Training: weighted binary cross-entropy with logits averaged over
+ * cells, gradients reduced over tiles in a fixed order, Adam (beta 0.9 /
+ * 0.999, eps 1e-8) on the FP32 master weights followed by a
+ * round-to-nearest-even BF16 copy.
+ *
+ * 2D (one tile = one patch of edge n = patch_cells, 8..32, even): input
+ * normalised (rho, u, v, p) of the patch plus 3 halo cells, pixel-major with
+ * 4 channels innermost ([ntile][(n+6)^2][4]); three valid 3x3 convolutions
+ * 4 -> 16 -> 16 -> 1, bias, ReLU after the first two; logits [ntile][n^2].
+ * Parameters (3057 floats): W1 [16][4][3][3], b1 [16], W2 [16][16][3][3],
+ * b2 [16], W3 [16][3][3], b3.
+ *
+ * 3D (tiles of 8^3 cells; patch_cells must be 8): input normalised
+ * (rho, u, v, w, p) of the tile plus 3 halo cells, voxel-major with 8
+ * channels innermost, the last 3 zero ([ntile][14^3][8]); three valid 3x3x3
+ * convolutions 5 -> 8 -> 8 -> 1; logits [ntile][8^3] (z, y, x order).
+ * Parameters (3041 floats): W1 [8][5][3][3][3], b1 [8], W2 [8][8][3][3][3],
+ * b2 [8], W3 [8][3][3][3], b3.  Prediction covers every leaf whose edge is a
+ * multiple of 8, tile by tile.
  * ---------------------------------------------------------------------- */
 typedef struct amr_cnn amr_cnn;
 typedef struct {
-  int patch_cells;   /* n: leaves whose edge is n are predicted */
-  float mean[4];     /* normalisation of (rho, u, v, p) */
-  float std[4];
+  int patch_cells;   /* 2D: leaves whose edge is n are predicted; 3D: 8 */
+  float mean[5];     /* normalisation of (rho, u, v, p) in 2D, (rho, u, v, w, p) in 3D */
+  float std[5];
   float pos_weight;  /* weight of the positive class in the loss */
-  int max_batch;     /* patches per forward/training call (1..4096) */
+  int max_batch;     /* tiles per forward/training call (1..4096) */
 } amr_cnn_config;
 
 /* Buffers of the predictor come from the hierarchy's allocator (sync). */
@@ -256,18 +266,18 @@ amr_status amr_cnn_num_params(const amr_cnn* c, int* n);
 /* FP32 master weights from / to the host (sync); setting resets Adam. */
 amr_status amr_cnn_set_weights(amr_cnn* c, const float* host_fp32, int n);
 amr_status amr_cnn_get_weights(amr_cnn* c, float* host_fp32, int n);
-/* Input tiles of the given leaf pids of buffer `buf` (ghosts filled first)
- * into x_dev (sync). */
+/* Input tiles of the given leaf pids (patches of edge patch_cells, one tile
+ * each) of buffer `buf` (ghosts filled first) into x_dev (sync). */
 amr_status amr_cnn_gather(amr_cnn* c, int buf, const int* pids_host, int npatch, uint16_t* x_dev);
 /* Logits of npatch <= max_batch input tiles (async). */
 amr_status amr_cnn_forward(amr_cnn* c, const uint16_t* x_dev, int npatch, float* logits_dev);
 /* Forward, loss (-> *loss_dev), backward; if lr > 0 one Adam step (async).
- * labels_dev: [npatch][n^2] bytes (0/1); grads_dev (nullable) receives the
+ * labels_dev: [npatch][n^d] bytes (0/1); grads_dev (nullable) receives the
  * summed parameter gradient. */
 amr_status amr_cnn_train_step(amr_cnn* c, const uint16_t* x_dev, const uint8_t* labels_dev,
                               int npatch, float lr, float* loss_dev, float* grads_dev);
-/* Predicted requests on buffer `buf` (sync): a leaf of edge n is flagged when
- * any cell has probability > tau; refine_req = flagged leaves below the
+/* Predicted requests on buffer `buf` (sync): a predicted leaf is flagged when
+ * any of its cells has probability > tau; refine_req = flagged leaves below the
  * finest level, coarsen_req = patches whose children are all unflagged
  * leaves (both per pid, max_patches bytes, device). */
 amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_dev,

@@ -61,7 +61,7 @@ class PatchInfo(C.Structure):
 
 
 class CnnConfig(C.Structure):
-    _fields_ = [("patch_cells", C.c_int), ("mean", C.c_float * 4), ("std", C.c_float * 4),
+    _fields_ = [("patch_cells", C.c_int), ("mean", C.c_float * 5), ("std", C.c_float * 5),
                 ("pos_weight", C.c_float), ("max_batch", C.c_int)]
 
 
@@ -418,17 +418,23 @@ class Hierarchy:
 
 
 class Predictor:
-    """The learned refinement predictor of a 2D hierarchy (device weights)."""
+    """The learned refinement predictor of a 2D or 3D hierarchy (device
+    weights).  ``mean``/``std`` normalise (rho, u, v, p) in 2D and
+    (rho, u, v, w, p) in 3D; a 3D tile has edge ``patch_cells`` = 8."""
 
     def __init__(self, hier: "Hierarchy", patch_cells: int, mean, std, pos_weight: float = 1.0,
                  max_batch: int = 256):
         self.hier = hier
         self.torch = hier.torch
+        self.dim = hier.cfg.dim
         self.n = patch_cells
         self.max_batch = max_batch
         c = CnnConfig()
         c.patch_cells = patch_cells
-        for k in range(4):
+        nch = self.dim + 2
+        if len(mean) != nch or len(std) != nch:
+            raise ValueError(f"{nch} normalisation channels expected")
+        for k in range(nch):
             c.mean[k] = float(mean[k])
             c.std[k] = float(std[k])
         c.pos_weight = pos_weight
@@ -456,7 +462,14 @@ class Predictor:
         return w
 
     def tile_shape(self):
-        return ((self.n + 6) ** 2, 4)
+        """(voxels, stored channels) of one input tile."""
+        if self.dim == 2:
+            return ((self.n + 6) ** 2, 4)
+        return ((self.n + 6) ** 3, 8)
+
+    @property
+    def tile_cells(self) -> int:
+        return self.n ** self.dim
 
     def gather(self, buf: int, pids):
         t = self.torch
@@ -467,7 +480,7 @@ class Predictor:
 
     def forward(self, x):
         t = self.torch
-        z = t.empty((x.shape[0], self.n * self.n), dtype=t.float32, device=self.hier.device)
+        z = t.empty((x.shape[0], self.tile_cells), dtype=t.float32, device=self.hier.device)
         self.hier._ok(_lib.amr_cnn_forward(self.h, Hierarchy._ptr(x), x.shape[0], Hierarchy._ptr(z)))
         return z
 

@@ -1259,7 +1259,9 @@ struct amr_cnn {
   amr_hierarchy* h = nullptr;
   amr_cnn_config cfg{};
   amr::CnnNorm norm{};
-  int n = 0, max_batch = 0, t = 0;
+  int dim = 2, n = 0, max_batch = 0, t = 0, np = 0;
+  long long in_elems = 0;   // BF16 values per input tile
+  long long out_cells = 0;  // logits per tile
   std::vector<void*> owned;
   float* params = nullptr;   // FP32 master
   float* m = nullptr;
@@ -1274,12 +1276,26 @@ struct amr_cnn {
   float* partials = nullptr;
   float* loss_part = nullptr;
   int loss_blocks = 0;
-  int* d_pids = nullptr;
+  int* d_pids = nullptr;   // 2D: pids; 3D: tile items
+  long long items_cap = 0;
   uint8_t* d_pred = nullptr;
   void* alloc(size_t bytes) {
     void* p = h->dev_alloc(bytes);
     owned.push_back(p);
     return p;
+  }
+  void gather(int buf, const int* items, int count, unsigned short* x) const {
+    if (dim == 2)
+      amr::Cnn::gather(h->dm, h->U[buf], items, count, n, norm, x, h->stream);
+    else
+      amr::Cnn3::gather(h->dm, h->U[buf], items, count, norm, x, h->stream);
+  }
+  void forward(const unsigned short* x, int count, unsigned short* a1, unsigned short* a2,
+               float* z) const {
+    if (dim == 2)
+      amr::Cnn::forward(count, n, x, wb, params, a1, a2, z, h->stream);
+    else
+      amr::Cnn3::forward(count, x, wb, params, a1, a2, z, h->stream);
   }
 };
 
@@ -1289,45 +1305,75 @@ amr_status amr_cnn_create(amr_hierarchy* h, const amr_cnn_config* cfg, amr_cnn**
   if (!h || !cfg || !out) return AMR_E_ARG;
   *out = nullptr;
   return guarded(h, [&]() -> amr_status {
-    if (h->cfg.dim != 2) throw ArgError("the predictor is implemented for 2D hierarchies");
-    if (cfg->patch_cells < 8 || cfg->patch_cells > 32 || cfg->patch_cells % 2)
+    const int dim = h->cfg.dim;
+    if (dim == 1) throw ArgError("the predictor is implemented for 2D and 3D hierarchies");
+    if (dim == 2 && (cfg->patch_cells < 8 || cfg->patch_cells > 32 || cfg->patch_cells % 2))
       throw ArgError("predictor patch edge must be even, 8..32");
+    if (dim == 3 && cfg->patch_cells != amr::CNN3_TILE)
+      throw ArgError("the 3D predictor works on tiles of edge 8 (patch_cells = 8)");
     if (cfg->max_batch < 1 || cfg->max_batch > 4096) throw ArgError("max_batch must be 1..4096");
+    const int nch = dim + 2;
+    for (int k = 0; k < nch; ++k)
+      if (!(cfg->std[k] > 0.f)) throw ArgError("normalisation std must be positive");
     amr_cnn* c = new amr_cnn();
     c->h = h;
     c->cfg = *cfg;
+    c->dim = dim;
     c->n = cfg->patch_cells;
     c->max_batch = cfg->max_batch;
-    for (int k = 0; k < 4; ++k) {
-      if (!(cfg->std[k] > 0.f)) {
-        delete c;
-        throw ArgError("normalisation std must be positive");
-      }
-      c->norm.mean[k] = cfg->mean[k];
-      c->norm.istd[k] = 1.0f / cfg->std[k];
+    for (int k = 0; k < 5; ++k) {
+      c->norm.mean[k] = k < nch ? cfg->mean[k] : 0.f;
+      c->norm.istd[k] = k < nch ? 1.0f / cfg->std[k] : 0.f;
     }
-    const int n = c->n, N = c->max_batch;
-    const long long P0 = (n + 6) * (n + 6), P1 = (n + 4) * (n + 4), P2 = (n + 2) * (n + 2);
-    c->params = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
-    c->m = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
-    c->v = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
-    c->grads = (float*)c->alloc(amr::CNN_NPARAM * sizeof(float));
-    c->wb = (unsigned short*)c->alloc(amr::CNN_NPARAM * sizeof(unsigned short));
-    c->X = (unsigned short*)c->alloc(N * P0 * 4 * sizeof(unsigned short));
-    c->A1 = (unsigned short*)c->alloc(N * P1 * 16 * sizeof(unsigned short));
-    c->A2 = (unsigned short*)c->alloc(N * P2 * 16 * sizeof(unsigned short));
-    c->Z = (float*)c->alloc((long long)N * n * n * sizeof(float));
-    c->G = (float*)c->alloc((long long)N * n * n * sizeof(float));
-    c->partials = (float*)c->alloc((long long)N * amr::CNN_NPARAM * sizeof(float));
-    c->loss_blocks = 256;
-    c->loss_part = (float*)c->alloc((c->loss_blocks + 1) * sizeof(float));
-    c->d_pids = (int*)c->alloc((size_t)h->forest.max_patches * sizeof(int));
-    c->d_pred = (uint8_t*)c->alloc(h->forest.max_patches);
-    HIP_OK(hipMemsetAsync(c->params, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
-    HIP_OK(hipMemsetAsync(c->m, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
-    HIP_OK(hipMemsetAsync(c->v, 0, amr::CNN_NPARAM * sizeof(float), h->stream));
-    HIP_OK(hipMemsetAsync(c->wb, 0, amr::CNN_NPARAM * sizeof(unsigned short), h->stream));
-    h->sync();
+    const int n = c->n;
+    const long long N = c->max_batch;
+    long long a1e, a2e;
+    if (dim == 2) {
+      c->np = amr::CNN_NPARAM;
+      c->in_elems = 4LL * (n + 6) * (n + 6);
+      a1e = 16LL * (n + 4) * (n + 4);
+      a2e = 16LL * (n + 2) * (n + 2);
+      c->out_cells = (long long)n * n;
+      c->items_cap = h->forest.max_patches;
+    } else {
+      c->np = amr::CNN3_NPARAM;
+      c->in_elems = (long long)amr::CNN3_CH * amr::CNN3_P0;
+      a1e = (long long)amr::CNN3_CH * amr::CNN3_P1;
+      a2e = (long long)amr::CNN3_CH * amr::CNN3_P2;
+      c->out_cells = amr::CNN3_P3;
+      int tiles = 1;
+      for (int l = 0; l < h->forest.nlev; ++l) {
+        const int e = h->forest.n[l] / amr::CNN3_TILE;
+        tiles = std::max(tiles, e * e * e);
+      }
+      c->items_cap = (long long)h->forest.max_patches * tiles;
+    }
+    const int np = c->np;
+    try {
+      c->params = (float*)c->alloc(np * sizeof(float));
+      c->m = (float*)c->alloc(np * sizeof(float));
+      c->v = (float*)c->alloc(np * sizeof(float));
+      c->grads = (float*)c->alloc(np * sizeof(float));
+      c->wb = (unsigned short*)c->alloc(np * sizeof(unsigned short));
+      c->X = (unsigned short*)c->alloc(N * c->in_elems * sizeof(unsigned short));
+      c->A1 = (unsigned short*)c->alloc(N * a1e * sizeof(unsigned short));
+      c->A2 = (unsigned short*)c->alloc(N * a2e * sizeof(unsigned short));
+      c->Z = (float*)c->alloc(N * c->out_cells * sizeof(float));
+      c->G = (float*)c->alloc(N * c->out_cells * sizeof(float));
+      c->partials = (float*)c->alloc(N * np * sizeof(float));
+      c->loss_blocks = 256;
+      c->loss_part = (float*)c->alloc((c->loss_blocks + 1) * sizeof(float));
+      c->d_pids = (int*)c->alloc((size_t)c->items_cap * sizeof(int));
+      c->d_pred = (uint8_t*)c->alloc(h->forest.max_patches);
+      HIP_OK(hipMemsetAsync(c->params, 0, np * sizeof(float), h->stream));
+      HIP_OK(hipMemsetAsync(c->m, 0, np * sizeof(float), h->stream));
+      HIP_OK(hipMemsetAsync(c->v, 0, np * sizeof(float), h->stream));
+      HIP_OK(hipMemsetAsync(c->wb, 0, np * sizeof(unsigned short), h->stream));
+      h->sync();
+    } catch (...) {
+      amr_cnn_destroy(c);
+      throw;
+    }
     *out = c;
     return AMR_OK;
   });
@@ -1349,17 +1395,17 @@ amr_status amr_cnn_destroy(amr_cnn* c) {
 
 amr_status amr_cnn_num_params(const amr_cnn* c, int* n) {
   if (!c || !n) return AMR_E_ARG;
-  *n = amr::CNN_NPARAM;
+  *n = c->np;
   return AMR_OK;
 }
 
 amr_status amr_cnn_set_weights(amr_cnn* c, const float* host, int n) {
-  if (!c || !host || n != amr::CNN_NPARAM) return AMR_E_ARG;
+  if (!c || !host || n != c->np) return AMR_E_ARG;
   return guarded(c->h, [&]() -> amr_status {
     HIP_OK(hipMemcpyAsync(c->params, host, n * sizeof(float), hipMemcpyHostToDevice, c->h->stream));
     HIP_OK(hipMemsetAsync(c->m, 0, n * sizeof(float), c->h->stream));
     HIP_OK(hipMemsetAsync(c->v, 0, n * sizeof(float), c->h->stream));
-    amr::Cnn::to_bf16(c->params, c->wb, c->h->stream);
+    amr::Cnn::to_bf16(c->params, c->np, c->wb, c->h->stream);
     c->h->check_launch();
     c->t = 0;
     c->h->sync();
@@ -1368,7 +1414,7 @@ amr_status amr_cnn_set_weights(amr_cnn* c, const float* host, int n) {
 }
 
 amr_status amr_cnn_get_weights(amr_cnn* c, float* host, int n) {
-  if (!c || !host || n != amr::CNN_NPARAM) return AMR_E_ARG;
+  if (!c || !host || n != c->np) return AMR_E_ARG;
   return guarded(c->h, [&]() -> amr_status {
     HIP_OK(hipMemcpyAsync(host, c->params, n * sizeof(float), hipMemcpyDeviceToHost, c->h->stream));
     c->h->sync();
@@ -1380,18 +1426,21 @@ amr_status amr_cnn_gather(amr_cnn* c, int buf, const int* pids_host, int npatch,
   if (!c || !buf_ok(buf) || npatch < 0 || (npatch > 0 && (!pids_host || !x_dev))) return AMR_E_ARG;
   return guarded(c->h, [&]() -> amr_status {
     amr_hierarchy* h = c->h;
+    if (npatch > h->forest.max_patches) throw ArgError("too many pids");
+    std::vector<int> items(npatch);
     for (int i = 0; i < npatch; ++i) {
       const int p = pids_host[i];
       if (p < 0 || p >= h->forest.max_patches || !h->forest.active[p] ||
           h->forest.n[h->forest.level[p]] != c->n)
         throw ArgError("gather: pid inactive or of another patch size");
+      // a 3D patch of edge 8 is the single tile 0
+      items[i] = c->dim == 2 ? p : p * amr::CNN3_MAX_TILES;
     }
-    if (npatch > h->forest.max_patches) throw ArgError("too many pids");
     do_fill(h, buf, h->leaves);
-    HIP_OK(hipMemcpyAsync(c->d_pids, pids_host, npatch * sizeof(int), hipMemcpyHostToDevice,
-                          h->stream));
-    amr::Cnn::gather(h->dm, h->U[buf], c->d_pids, npatch, c->n, c->norm, (unsigned short*)x_dev,
-                     h->stream);
+    if (npatch > 0)
+      HIP_OK(hipMemcpyAsync(c->d_pids, items.data(), npatch * sizeof(int), hipMemcpyHostToDevice,
+                            h->stream));
+    c->gather(buf, c->d_pids, npatch, (unsigned short*)x_dev);
     h->check_launch();
     h->sync();
     return AMR_OK;
@@ -1401,8 +1450,7 @@ amr_status amr_cnn_gather(amr_cnn* c, int buf, const int* pids_host, int npatch,
 amr_status amr_cnn_forward(amr_cnn* c, const uint16_t* x_dev, int npatch, float* logits_dev) {
   if (!c || !x_dev || !logits_dev || npatch < 0 || npatch > c->max_batch) return AMR_E_ARG;
   return guarded(c->h, [&]() -> amr_status {
-    amr::Cnn::forward(npatch, c->n, (const unsigned short*)x_dev, c->wb, c->params, nullptr,
-                      nullptr, logits_dev, c->h->stream);
+    c->forward((const unsigned short*)x_dev, npatch, nullptr, nullptr, logits_dev);
     c->h->check_launch();
     return AMR_OK;
   });
@@ -1415,17 +1463,19 @@ amr_status amr_cnn_train_step(amr_cnn* c, const uint16_t* x_dev, const uint8_t* 
   return guarded(c->h, [&]() -> amr_status {
     hipStream_t s = c->h->stream;
     const unsigned short* X = (const unsigned short*)x_dev;
-    amr::Cnn::forward(npatch, c->n, X, c->wb, c->params, c->A1, c->A2, c->Z, s);
-    const long long total = (long long)npatch * c->n * c->n;
+    c->forward(X, npatch, c->A1, c->A2, c->Z);
+    const long long total = (long long)npatch * c->out_cells;
     amr::Cnn::loss(total, c->Z, labels_dev, c->cfg.pos_weight, c->G, c->loss_part,
                    c->loss_blocks, loss_dev, s);
-    amr::Cnn::backward(npatch, c->n, X, c->A1, c->A2, c->G, c->wb, c->partials, c->grads, s);
+    if (c->dim == 2)
+      amr::Cnn::backward(npatch, c->n, X, c->A1, c->A2, c->G, c->wb, c->partials, c->grads, s);
+    else
+      amr::Cnn3::backward(npatch, X, c->A1, c->A2, c->G, c->wb, c->partials, c->grads, s);
     if (grads_dev)
-      HIP_OK(hipMemcpyAsync(grads_dev, c->grads, amr::CNN_NPARAM * sizeof(float),
-                            hipMemcpyDeviceToDevice, s));
+      HIP_OK(hipMemcpyAsync(grads_dev, c->grads, c->np * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (lr > 0.f) {
       c->t += 1;
-      amr::Cnn::adam(c->params, c->grads, c->m, c->v, lr, c->t, c->wb, s);
+      amr::Cnn::adam(c->params, c->grads, c->m, c->v, lr, c->t, c->np, c->wb, s);
     }
     c->h->check_launch();
     return AMR_OK;
@@ -1438,26 +1488,40 @@ amr_status amr_cnn_predict(amr_cnn* c, int buf, float tau, uint8_t* refine_req_d
   return guarded(c->h, [&]() -> amr_status {
     amr_hierarchy* h = c->h;
     hipStream_t s = h->stream;
-    std::vector<int> pids;
-    for (int pid = 0; pid < h->forest.max_patches; ++pid)
-      if (h->forest.active[pid] && h->forest.is_leaf(pid) && h->forest.n[h->forest.level[pid]] == c->n)
-        pids.push_back(pid);
+    const amr::Forest& f = h->forest;
+    // 2D: leaves of edge n; 3D: every 8^3 tile of the leaves whose edge is a
+    // multiple of 8
+    std::vector<int> items;
+    for (int pid = 0; pid < f.max_patches; ++pid) {
+      if (!f.active[pid] || !f.is_leaf(pid)) continue;
+      const int e = f.n[f.level[pid]];
+      if (c->dim == 2) {
+        if (e == c->n) items.push_back(pid);
+      } else if (e % amr::CNN3_TILE == 0) {
+        const int nt = e / amr::CNN3_TILE;
+        for (int t = 0; t < nt * nt * nt; ++t) items.push_back(pid * amr::CNN3_MAX_TILES + t);
+      }
+    }
+    if ((long long)items.size() > c->items_cap) throw ArgError("predictor item list overflow");
     do_fill(h, buf, h->leaves);
-    HIP_OK(hipMemsetAsync(c->d_pred, 0, h->forest.max_patches, s));
-    if (!pids.empty())
-      HIP_OK(hipMemcpyAsync(c->d_pids, pids.data(), pids.size() * sizeof(int),
+    HIP_OK(hipMemsetAsync(c->d_pred, 0, f.max_patches, s));
+    if (!items.empty())
+      HIP_OK(hipMemcpyAsync(c->d_pids, items.data(), items.size() * sizeof(int),
                             hipMemcpyHostToDevice, s));
     const float zt = std::log(tau / (1.0f - tau));
-    for (size_t b0 = 0; b0 < pids.size(); b0 += (size_t)c->max_batch) {
-      const int cnt = (int)std::min<size_t>(c->max_batch, pids.size() - b0);
-      amr::Cnn::gather(h->dm, h->U[buf], c->d_pids + b0, cnt, c->n, c->norm, c->X, s);
-      amr::Cnn::forward(cnt, c->n, c->X, c->wb, c->params, nullptr, nullptr, c->Z, s);
-      amr::Cnn::requests(cnt, c->n, c->Z, c->d_pids + b0, zt, c->d_pred, s);
+    for (size_t b0 = 0; b0 < items.size(); b0 += (size_t)c->max_batch) {
+      const int cnt = (int)std::min<size_t>(c->max_batch, items.size() - b0);
+      c->gather(buf, c->d_pids + b0, cnt, c->X);
+      c->forward(c->X, cnt, nullptr, nullptr, c->Z);
+      if (c->dim == 2)
+        amr::Cnn::requests(cnt, c->n, c->Z, c->d_pids + b0, zt, c->d_pred, s);
+      else
+        amr::Cnn3::requests(cnt, c->Z, c->d_pids + b0, zt, c->d_pred, s);
     }
-    Kernels::requests(h->dm, c->d_pred, h->d_active_leaf, h->forest.max_patches, refine_req_dev,
+    Kernels::requests(h->dm, c->d_pred, h->d_active_leaf, f.max_patches, refine_req_dev,
                       coarsen_req_dev, s);
     h->check_launch();
-    h->sync();  // pids (host vector) copied
+    h->sync();  // items (host vector) copied
     return AMR_OK;
   });
 }

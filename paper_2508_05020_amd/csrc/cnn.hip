@@ -8,57 +8,22 @@
 // with the channels innermost (HWC), so that the 4 consecutive channels an
 // MFMA lane needs are one 8-byte load.
 //
-// MFMA used: v_mfma_f32_16x16x16_bf16 (__builtin_amdgcn_mfma_f32_16x16x16bf16_1k).
-// Operand layout per lane l (0..63), element e (0..3):
-//   A[i][k]: i = l % 16, k = 4 (l / 16) + e
-//   B[k][j]: j = l % 16, k = 4 (l / 16) + e
-//   D[i][j]: j = l % 16, i = 4 (l / 16) + e
-// (checked on the device by amr_cnn_mfma_selftest).
+// MFMA operand layout: see cnn_device.hpp.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 
 #include "amr_internal.hpp"
+#include "cnn_device.hpp"
 #include "cnn_internal.hpp"
 
 namespace amr {
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
+using namespace cnnd;
 
 constexpr int NG = kNG;
-
-__device__ __forceinline__ unsigned short f2bf(float f) {
-  // round to nearest even
-  unsigned int u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
-
-__device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ s4 load4(const unsigned short* p) {
-  // p is 8-byte aligned (4 channels of one pixel)
-  const uint2 v = *reinterpret_cast<const uint2*>(p);
-  s4 r;
-  r.x = (short)(v.x & 0xffff);
-  r.y = (short)(v.x >> 16);
-  r.z = (short)(v.y & 0xffff);
-  r.w = (short)(v.y >> 16);
-  return r;
-}
-
-__device__ __forceinline__ s4 zero4() {
-  s4 r = {0, 0, 0, 0};
-  return r;
-}
 
 // ---------------------------------------------------------------------------
 // gather: normalised BF16 input tiles from the FP64 state (ghosts filled)
@@ -435,20 +400,21 @@ __global__ __launch_bounds__(BWD_THREADS) void k_cnn_bwd(int count, int n,
 }
 
 // deterministic sum of the per-patch partials (fixed order over patches)
-__global__ void k_cnn_reduce(const float* __restrict__ partials, int count, float* __restrict__ grads) {
+__global__ void k_cnn_reduce(const float* __restrict__ partials, int count, int np,
+                             float* __restrict__ grads) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= CNN_NPARAM) return;
+  if (k >= np) return;
   float s = 0.f;
-  for (int b = 0; b < count; ++b) s += partials[(long long)b * CNN_NPARAM + k];
+  for (int b = 0; b < count; ++b) s += partials[(long long)b * np + k];
   grads[k] = s;
 }
 
 // Adam on FP32 master weights, then the BF16 copy (round to nearest even)
 __global__ void k_cnn_adam(float* __restrict__ params, const float* __restrict__ grads,
                            float* __restrict__ m, float* __restrict__ v, float lr, float c1,
-                           float c2, unsigned short* __restrict__ Wb) {
+                           float c2, int np, unsigned short* __restrict__ Wb) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= CNN_NPARAM) return;
+  if (k >= np) return;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   const float g = grads[k];
   const float mk = b1 * m[k] + (1.f - b1) * g;
@@ -461,9 +427,9 @@ __global__ void k_cnn_adam(float* __restrict__ params, const float* __restrict__
   Wb[k] = f2bf(p);
 }
 
-__global__ void k_cnn_to_bf16(const float* __restrict__ params, unsigned short* __restrict__ Wb) {
+__global__ void k_cnn_to_bf16(const float* __restrict__ params, int np, unsigned short* __restrict__ Wb) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < CNN_NPARAM) Wb[k] = f2bf(params[k]);
+  if (k < np) Wb[k] = f2bf(params[k]);
 }
 
 // per-patch refine request: any logit above the threshold
@@ -553,20 +519,24 @@ void Cnn::backward(int count, int n, const unsigned short* X, const unsigned sho
   allow_large_lds();
   hipLaunchKernelGGL(k_cnn_bwd, dim3(count), dim3(BWD_THREADS), bwd_lds(n), s, count, n, X, A1, A2,
                      G, Wb, partials);
-  hipLaunchKernelGGL(k_cnn_reduce, dim3((CNN_NPARAM + 255) / 256), dim3(256), 0, s, partials,
-                     count, grads);
+  reduce(partials, count, CNN_NPARAM, grads, s);
 }
 
-void Cnn::adam(float* params, const float* grads, float* m, float* v, float lr, int t,
+void Cnn::reduce(const float* partials, int count, int np, float* grads, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_reduce, dim3((np + 255) / 256), dim3(256), 0, s, partials, count, np,
+                     grads);
+}
+
+void Cnn::adam(float* params, const float* grads, float* m, float* v, float lr, int t, int np,
                unsigned short* Wb, hipStream_t s) {
   const float c1 = 1.f - powf(0.9f, (float)t);
   const float c2 = 1.f - powf(0.999f, (float)t);
-  hipLaunchKernelGGL(k_cnn_adam, dim3((CNN_NPARAM + 255) / 256), dim3(256), 0, s, params, grads, m,
-                     v, lr, c1, c2, Wb);
+  hipLaunchKernelGGL(k_cnn_adam, dim3((np + 255) / 256), dim3(256), 0, s, params, grads, m, v, lr,
+                     c1, c2, np, Wb);
 }
 
-void Cnn::to_bf16(const float* params, unsigned short* Wb, hipStream_t s) {
-  hipLaunchKernelGGL(k_cnn_to_bf16, dim3((CNN_NPARAM + 255) / 256), dim3(256), 0, s, params, Wb);
+void Cnn::to_bf16(const float* params, int np, unsigned short* Wb, hipStream_t s) {
+  hipLaunchKernelGGL(k_cnn_to_bf16, dim3((np + 255) / 256), dim3(256), 0, s, params, np, Wb);
 }
 
 void Cnn::requests(int count, int n, const float* Z, const int* pids, float zt, uint8_t* flag,

@@ -6,8 +6,9 @@ sequences calls and moves small host-side arrays.
 Labels come from the solver itself: for a patch at step t, a cell is positive
 when the plain gradient tagger tags it (after dilation) at any step in
 (t, t + horizon].  Training data are recorded on single-level periodic runs
-of the 2D quadrant + blob generator at several resolutions, so that the
-network sees features at the cell sizes of several AMR levels.
+at several resolutions (the 2D quadrant + blob generator, or the 3D blast +
+perturbation generator), so that the network sees features at the cell sizes
+of several AMR levels.  In 3D a training patch is one 8^3 tile.
 
 Policies (wall-clock per unit simulated time is the figure of merit):
   plain  -- gradient tagging + regrid every ``every`` steps;
@@ -32,30 +33,40 @@ from . import amr as A
 from . import workloads as W
 
 
-def init_weights(seed: int) -> np.ndarray:
+def net_shape(dim: int):
+    """(input channels, hidden channels, taps) of the network."""
+    return (4, 16, 9) if dim == 2 else (5, 8, 27)
+
+
+def init_weights(seed: int, dim: int = 2) -> np.ndarray:
     """He-normal weights, zero biases, in the flat parameter layout of the
-    library (W1 [16][4][3][3], b1, W2 [16][16][3][3], b2, W3 [16][3][3], b3)."""
+    library: W1 [C1][C0][taps], b1, W2 [C1][C1][taps], b2, W3 [C1][taps], b3
+    with (C0, C1, taps) = (4, 16, 3x3) in 2D and (5, 8, 3x3x3) in 3D."""
+    c0, c1, k = net_shape(dim)
     rng = np.random.default_rng(seed)
-    parts = [rng.normal(0.0, math.sqrt(2.0 / (4 * 9)), 16 * 4 * 9), np.zeros(16),
-             rng.normal(0.0, math.sqrt(2.0 / (16 * 9)), 16 * 16 * 9), np.zeros(16),
-             rng.normal(0.0, math.sqrt(2.0 / (16 * 9)), 16 * 9), np.zeros(1)]
+    parts = [rng.normal(0.0, math.sqrt(2.0 / (c0 * k)), c1 * c0 * k), np.zeros(c1),
+             rng.normal(0.0, math.sqrt(2.0 / (c1 * k)), c1 * c1 * k), np.zeros(c1),
+             rng.normal(0.0, math.sqrt(2.0 / (c1 * k)), c1 * k), np.zeros(1)]
     return np.concatenate(parts).astype(np.float32)
 
 
 def uniform_config(base: int, n: int = 32, tag_buffer: int = 2, cfl: float = 0.5,
-                   max_patches: int = 4096) -> W.AMRConfig:
-    return W.AMRConfig(name=f"uniform{base}", dim=2, base_cells=base, patch_cells=[n],
-                       periodic=[True, True], cfl=cfl, tag_buffer=tag_buffer,
-                       ic="quadrants_blobs", max_patches=max_patches, regrid_interval=0)
+                   max_patches: int = 4096, dim: int = 2) -> W.AMRConfig:
+    ic = "quadrants_blobs" if dim == 2 else "blasts_perturbed"
+    return W.AMRConfig(name=f"uniform{base}", dim=dim, base_cells=base, patch_cells=[n],
+                       periodic=[True] * dim, cfl=cfl, tag_buffer=tag_buffer,
+                       ic=ic, max_patches=max_patches, regrid_interval=0)
 
 
 def _cell_tags(h: A.Hierarchy, cells, pids: Sequence[int], n: int) -> np.ndarray:
+    d = h.cfg.dim
     flat = cells.cpu().numpy()
-    out = np.zeros((len(pids), n * n), np.uint8)
+    out = np.zeros((len(pids), n ** d), np.uint8)
+    inner = (slice(4, -4),) * d
     for b, pid in enumerate(pids):
         off = h.offset(pid) // h.nvar
-        box = flat[off:off + (n + 8) ** 2].reshape(n + 8, n + 8)
-        out[b] = box[4:-4, 4:-4].ravel()
+        box = flat[off:off + (n + 8) ** d].reshape((n + 8,) * d)
+        out[b] = box[inner].ravel()
     return out
 
 
@@ -89,33 +100,37 @@ def record(cfg: W.AMRConfig, seed: int, steps: int, horizon: int, stride: int,
 
 
 def input_statistics(cfgs, seeds, steps=16):
-    """Per-channel mean and standard deviation of (rho, u, v, p) over the
-    recorded pixels (inputs gathered without normalisation)."""
+    """Per-channel mean and standard deviation of (rho, u, v, p) (2D) or
+    (rho, u, v, w, p) (3D) over the recorded pixels (inputs gathered without
+    normalisation)."""
     vals = []
     for cfg in cfgs:
+        nch = cfg.dim + 2
         for seed in seeds:
-            x, _ = record(cfg, seed, steps, horizon=1, stride=4, mean=(0, 0, 0, 0), std=(1, 1, 1, 1))
+            x, _ = record(cfg, seed, steps, horizon=1, stride=4, mean=(0,) * nch, std=(1,) * nch)
             u = x.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
-            vals.append(u.view(np.float32).reshape(-1, 4))
+            vals.append(u.view(np.float32).reshape(-1, x.shape[-1])[:, :nch])
     v = np.concatenate(vals).astype(np.float64)
     return v.mean(axis=0), np.maximum(v.std(axis=0), 1e-3)
 
 
 @dataclasses.dataclass
 class Dataset:
-    x: object            # torch int16 [S, (n+6)^2, 4] on the device
-    y: np.ndarray        # uint8 [S, n^2]
+    x: object            # torch int16 [S, (n+6)^d, channels] on the device
+    y: np.ndarray        # uint8 [S, n^d]
     n: int
 
 
 def build_dataset(resolutions: Sequence[int], seeds: Sequence[int], steps: int, horizon: int,
-                  stride: int, mean, std, n: int = 32, tag_buffer: int = 2) -> Dataset:
+                  stride: int, mean, std, n: int = 32, tag_buffer: int = 2,
+                  dim: int = 2) -> Dataset:
     """Inputs and labels of single-level runs at the given resolutions, the
     labels dilated by `tag_buffer` cells like the tagger they forecast."""
     torch = A._torch()
     xs, ys = [], []
     for base in resolutions:
-        cfg = uniform_config(base, n, tag_buffer=tag_buffer)
+        cfg = uniform_config(base, n, tag_buffer=tag_buffer, dim=dim,
+                             max_patches=max(4096, (base // n) ** dim))
         for seed in seeds:
             x, y = record(cfg, seed, steps, horizon, stride, mean, std)
             xs.append(x)
