@@ -81,6 +81,11 @@ def measured_traffic(variant, cells_per_launch):
     return (v["fetch_bytes_per_cell"] + v["write_bytes_per_cell"]) * cells_per_launch
 
 
+# largest base grid whose initial hierarchy the oracle steps within about a
+# minute on one host core (2D 512^2)
+ORACLE_MAX_BASE_CELLS = 1 << 18
+
+
 def cpu_baseline(cfg, seed: int):
     """The oracle, as it stands, on a bounded sample: one SSP-RK3 step over the
     initial hierarchy of the same workload."""
@@ -118,34 +123,47 @@ def copy_calibration() -> int:
 
 def learned_gain(args) -> int:
     """Train the refinement predictor on the solver's own tags, then compare
-    regridding policies on one seeded 2D quadrant + blob run: wall-clock per
-    unit simulated time, judge failures (fallbacks), regrids and cell
-    updates.  Every policy runs under the plain-tag judge with fallback, so
-    all advance on meshes that cover the plain tags at the same rate."""
+    regridding policies on one seeded run (2D quadrants + blobs, or 3D blast
+    waves + density perturbations): wall-clock per unit simulated time, judge
+    failures (fallbacks), regrids and cell updates.  Every policy runs under
+    the plain-tag judge with fallback, so all advance on meshes that cover the
+    plain tags at the same rate."""
     import numpy as np
     from paper_2508_05020_amd import amr, learned, workloads
 
-    n, H, b = 16, args.learned_every, args.learned_buffer
-    cfg = workloads.AMRConfig(name="quadrants-blobs-4lev", dim=2, base_cells=64,
-                              patch_cells=[n] * 4, periodic=[True, True], ic="quadrants_blobs",
-                              tag_buffer=b, max_patches=16384)
-    seeds = list(range(4000, 4000 + args.train_runs))
+    H, b, dim = args.learned_every, args.learned_buffer, args.learned_dim
+    seed_eval = args.seed_eval if args.seed_eval is not None else (4100 if dim == 2 else 5100)
+    rounds = args.learned_rounds if args.learned_rounds is not None else (1 if dim == 2 else 2)
+    if dim == 2:
+        n = 16
+        cfg = workloads.AMRConfig(name="quadrants-blobs-4lev", dim=2, base_cells=64,
+                                  patch_cells=[n] * 4, periodic=[True, True],
+                                  ic="quadrants_blobs", tag_buffer=b, max_patches=16384)
+        seeds = list(range(4000, 4000 + args.train_runs))
+        stride = 2
+    else:
+        n = 8
+        cfg = workloads.AMRConfig(name="blasts-perturbed-4lev", dim=3, base_cells=16,
+                                  patch_cells=[n] * 4, periodic=[True] * 3,
+                                  ic="blasts_perturbed", tag_buffer=b, max_patches=32768)
+        seeds = list(range(5000, 5000 + args.train_runs))
+        stride = 4
     res = tuple(cfg.base_cells * 2 ** l for l in range(cfg.max_levels))
     t0 = time.perf_counter()
-    mean, std = learned.input_statistics([learned.uniform_config(cfg.base_cells, n, tag_buffer=b)],
-                                         seeds[:1], steps=8)
-    data = learned.build_dataset(res, seeds, steps=40, horizon=H, stride=2, mean=mean, std=std,
-                                 n=n, tag_buffer=b)
-    val = learned.build_dataset(res[-2:], [args.seed_eval], steps=40, horizon=H, stride=4,
-                                mean=mean, std=std, n=n, tag_buffer=b)
+    mean, std = learned.input_statistics(
+        [learned.uniform_config(cfg.base_cells, n, tag_buffer=b, dim=dim)], seeds[:1], steps=8)
+    data = learned.build_dataset(res, seeds, steps=40, horizon=H, stride=stride, mean=mean,
+                                 std=std, n=n, tag_buffer=b, dim=dim)
+    val = learned.build_dataset(res[-2:], [seed_eval], steps=40, horizon=H, stride=4,
+                                mean=mean, std=std, n=n, tag_buffer=b, dim=dim)
     pos = float(data.y.mean())
     pos_weight = float(min(100.0, (1.0 - pos) / max(pos, 1e-6)))
-    log(f"[learned] {data.x.shape[0]} training patches from {len(seeds)} runs at {res}, "
+    log(f"[learned] {data.x.shape[0]} training tiles from {len(seeds)} runs at {res}, "
         f"positive cells {pos:.3f} ({time.perf_counter() - t0:.1f} s)")
 
     def hier(mode=amr.EXEC_BATCHED):
         h = amr.Hierarchy(cfg, exec_mode=mode)
-        amr.init_from_ic(h, workloads.initial_data(cfg, args.seed_eval))
+        amr.init_from_ic(h, workloads.initial_data(cfg, seed_eval))
         return h
 
     h = hier()
@@ -153,7 +171,7 @@ def learned_gain(args) -> int:
     h.close()
     h_bl = hier()
     pred = amr.Predictor(h_bl, n, mean, std, pos_weight=pos_weight, max_batch=256)
-    pred.set_weights(learned.init_weights(seed=1))
+    pred.set_weights(learned.init_weights(seed=1, dim=dim))
     t1 = time.perf_counter()
     losses = learned.train(pred, data, epochs=args.epochs, lr=2e-3, batch=64)
     train_s = time.perf_counter() - t1
@@ -171,16 +189,18 @@ def learned_gain(args) -> int:
                                       (f"learned{H}", H, "learned", amr.EXEC_BATCHED)):
         h = h_bl if policy == "learned" else hier(mode)
         st = learned.run_policy(h, steps, every, policy, pred if policy == "learned" else None,
-                                tau, judge=True)
+                                tau, judge=True, rounds=rounds)
         results[name] = st.as_dict()
         log(f"[learned] {name}: {results[name]}")
         if policy != "learned":
             h.close()
     L = results[f"learned{H}"]["wall_per_tsim"]
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
-           "config": {"workload": f"{cfg.name}: 2D base {cfg.base_cells}^2, {cfg.max_levels} levels of "
-                                  f"{n}^2 patches, dilation {b}, seed {args.seed_eval}, {steps} steps"},
-           "training": {"patches": int(data.x.shape[0]), "runs": len(seeds), "horizon": H,
+           "config": {"workload": f"{cfg.name}: {dim}D base {cfg.base_cells}^{dim}, {cfg.max_levels} "
+                                  f"levels of {n}^{dim} patches, dilation {b}, seed {seed_eval}, "
+                                  f"{steps} steps"},
+           "learned_rounds": rounds,
+           "training": {"tiles": int(data.x.shape[0]), "runs": len(seeds), "horizon": H,
                         "epochs": args.epochs, "first_loss": losses[0], "final_loss": losses[-1],
                         "seconds": train_s, "tau": tau, "validation": met},
            "policies": results,
@@ -215,7 +235,13 @@ def main() -> int:
     ap.add_argument("--learned-every", type=int, default=16,
                     help="regrid interval of the learned policy (and forecast horizon)")
     ap.add_argument("--learned-buffer", type=int, default=1, help="tag dilation in cells")
-    ap.add_argument("--seed-eval", type=int, default=4100)
+    ap.add_argument("--learned-rounds", type=int, default=None,
+                    help="predict + regrid rounds per learned regrid (each can add one level; "
+                         "default 1 in 2D, 2 in 3D)")
+    ap.add_argument("--learned-dim", type=int, default=2, choices=[2, 3],
+                    help="2D quadrants + blobs or 3D blast waves + perturbations")
+    ap.add_argument("--seed-eval", type=int, default=None,
+                    help="seed of the evaluation run (default 4100 in 2D, 5100 in 3D)")
     ap.add_argument("--train-runs", type=int, default=3)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -366,8 +392,14 @@ def main() -> int:
         },
     }
     if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+        if cfg.base_cells ** cfg.dim > ORACLE_MAX_BASE_CELLS:
+            # one oracle step over this initial hierarchy would take hours
+            out["cpu_baseline"] = None
+            log(f"[bench] no cpu_baseline: {cfg.base_cells}^{cfg.dim} base cells is beyond the "
+                f"oracle's bounded sample ({ORACLE_MAX_BASE_CELLS})")
+        else:
+            log("[bench] timing the oracle on a bounded sample")
+            out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
     print(json.dumps(out), flush=True)
     h.close()
     return 0

@@ -180,6 +180,8 @@ def make_config(cfg, exec_mode: int = EXEC_BATCHED, coarsen_rule: int = COARSEN_
     c.gamma, c.cfl, c.weno_eps, c.tag_theta = cfg.gamma, cfg.cfl, cfg.weno_eps, cfg.tag_theta
     c.tag_buffer = cfg.tag_buffer
     c.max_patches = cfg.max_patches
+    if level_capacity is None:
+        level_capacity = getattr(cfg, "level_capacity", ())
     if level_capacity:
         for l, v in enumerate(level_capacity):
             c.level_capacity[l] = v

@@ -58,16 +58,15 @@ def uniform_config(base: int, n: int = 32, tag_buffer: int = 2, cfl: float = 0.5
                        ic=ic, max_patches=max_patches, regrid_interval=0)
 
 
-def _cell_tags(h: A.Hierarchy, cells, pids: Sequence[int], n: int) -> np.ndarray:
+def _interior_index(h: A.Hierarchy, pids: Sequence[int], n: int):
+    """Device index of the interior cells of the given patches in the
+    hierarchy's cell-tag layout, [len(pids), n^d] (row-major interior)."""
+    torch = A._torch()
     d = h.cfg.dim
-    flat = cells.cpu().numpy()
-    out = np.zeros((len(pids), n ** d), np.uint8)
-    inner = (slice(4, -4),) * d
-    for b, pid in enumerate(pids):
-        off = h.offset(pid) // h.nvar
-        box = flat[off:off + (n + 8) ** d].reshape((n + 8,) * d)
-        out[b] = box[inner].ravel()
-    return out
+    box = np.arange((n + 8) ** d, dtype=np.int64).reshape((n + 8,) * d)
+    inner = box[(slice(4, -4),) * d].ravel()
+    base = np.array([h.offset(pid) // h.nvar for pid in pids], np.int64)
+    return torch.from_numpy(base[:, None] + inner[None, :]).to(h.device)
 
 
 def record(cfg: W.AMRConfig, seed: int, steps: int, horizon: int, stride: int,
@@ -79,6 +78,7 @@ def record(cfg: W.AMRConfig, seed: int, steps: int, horizon: int, stride: int,
     n = cfg.patch_cells[0]
     pred = A.Predictor(h, n, mean, std, max_batch=1)
     pids = [r["pid"] for r in h.patch_table()]
+    idx = _interior_index(h, pids, n)
     xs, tags = [], []
     snaps = []
     for t in range(steps + horizon + 1):
@@ -86,12 +86,12 @@ def record(cfg: W.AMRConfig, seed: int, steps: int, horizon: int, stride: int,
             xs.append(pred.gather(0, pids))
             snaps.append(t)
         _, _, cells = h.tag(0, cell_tags=True)
-        tags.append(_cell_tags(h, cells, pids, n))
+        tags.append(cells[idx].cpu().numpy())
         h.step()
     ys = []
     for t in snaps:
-        y = np.zeros_like(tags[0])
-        for s in range(t + 1, t + horizon + 1):
+        y = tags[t + 1].copy()
+        for s in range(t + 2, t + horizon + 1):
             y |= tags[s]
         ys.append(y)
     pred.close()

@@ -51,6 +51,8 @@ class AMRConfig:
     max_patches: int = 4096
     ic: str = "uniform"
     ghost: int = 4
+    # patch slots per level (0 = level 0 exact / the rest shared equally)
+    level_capacity: tuple = ()
 
     @property
     def max_levels(self) -> int:
@@ -114,10 +116,13 @@ CONFIGS = {
     "c4": _cfg(name="c4", dim=2, base_cells=512, patch_cells=[32] * 5,
                periodic=[True, True], steps=200, regrid_interval=8,
                tag_buffer=2, ic="quadrants_blobs", max_patches=65536),
-    # 3D blast waves + k^-2 density perturbations, base 256^3.
+    # 3D blast waves + k^-2 density perturbations, base 256^3; each refined
+    # 16^3 level-2 patch has 64 children of 8^3, so level 3 holds most of the
+    # ~175k patches (about 150 M leaf cells; the pools take ~170 GB).
     "c5": _cfg(name="c5", dim=3, base_cells=256, patch_cells=[32, 16, 16, 8],
                periodic=[True] * 3, steps=200, regrid_interval=8, tag_buffer=2,
-               ic="blasts_perturbed", max_patches=131072),
+               ic="blasts_perturbed", max_patches=512 + 8192 + 16384 + 262144,
+               level_capacity=(512, 8192, 16384, 262144)),
     # The paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2.
     "implosion": _cfg(name="implosion", dim=2, base_cells=256,
                       patch_cells=[32, 16, 16], periodic=[True, True],
@@ -307,16 +312,58 @@ def blasts_perturbed(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0,
                 modes.append((k, kk ** -1.0))
     phases = rng.uniform(0.0, 2.0 * np.pi, len(modes))
     total = sum(a for _, a in modes)
+    # complex coefficients on the dense (k_z, k_y, k_x) grid; zero off the modes
+    K = 2 * kmax + 1
+    coef = np.zeros((K,) * dim, np.complex128)
+    for (k, a), ph in zip(modes, phases):
+        coef[tuple(c + kmax for c in reversed(k))] = (amp * a / total) * np.exp(1j * ph)
+    ks = np.arange(-kmax, kmax + 1)
+
+    def axis_values(pts):
+        """Per-axis coordinates if pts is a tensor grid in (z, y, x) array
+        order (as patch_points makes them), else None."""
+        if pts[0].ndim != dim:
+            return None
+        vals = []
+        for j in range(dim):
+            ax = dim - 1 - j
+            idx = [0] * dim
+            idx[ax] = slice(None)
+            v = pts[j][tuple(idx)]
+            shp = [1] * dim
+            shp[ax] = v.size
+            if not np.array_equal(np.broadcast_to(v.reshape(shp), pts[j].shape), pts[j]):
+                return None
+            vals.append(v)
+        return vals
+
+    def perturbation(pts):
+        # sum_k c_k prod_j exp(i 2 pi k_j (x_j - lo) / L), contracted one axis
+        # at a time (x, then y, then z); the real part is the cosine sum
+        g = axis_values(pts)
+        if g is not None:
+            e = [np.exp((2j * np.pi / L) * np.outer(ks, g[j] - lo)) for j in range(dim)]
+            t = np.tensordot(coef, e[0], axes=([dim - 1], [0]))      # [..., k_y, x]
+            for j in range(1, dim):
+                # contract the last remaining wave-number axis (k_y, then k_z)
+                t = np.tensordot(t, e[j], axes=([dim - 1 - j], [0]))  # new axis last
+            # axes are now (x, y, z): back to (z, y, x)
+            return np.transpose(t.real, tuple(range(dim - 1, -1, -1)))
+        shape = pts[0].shape
+        flat = [np.ravel(q) for q in pts]
+        out = np.empty(flat[0].size)
+        for q0 in range(0, out.size, 8192):
+            sl = slice(q0, min(out.size, q0 + 8192))
+            e = [np.exp((2j * np.pi / L) * np.outer(ks, flat[j][sl] - lo)) for j in range(dim)]
+            t = coef.reshape(-1, K) @ e[0]
+            for j in range(1, dim):
+                t = (t.reshape(-1, K, e[j].shape[1]) * e[j][None]).sum(axis=1)
+            out[sl] = t.reshape(-1).real
+        return out.reshape(shape)
 
     def f(pts):
         p = _blast_pressure(src, pts, dim, L)
-        drho = np.zeros_like(pts[0])
-        for (k, a), ph in zip(modes, phases):
-            arg = np.full_like(pts[0], ph)
-            for j in range(dim):
-                arg = arg + 2.0 * np.pi * k[j] * (pts[j] - lo) / L
-            drho = drho + (amp * a / total) * np.cos(arg)
-        return (1.0 + drho, [np.zeros_like(p) for _ in range(dim)], p)
+        return (1.0 + perturbation(pts), [np.zeros_like(p) for _ in range(dim)], p)
     return f
 
 
