@@ -28,6 +28,12 @@ def case_config(name: str):
         cfg = W.AMRConfig(name="p2w", dim=2, base_cells=64, patch_cells=[16, 16, 16],
                           periodic=[False, True], ic="quadrants_blobs", max_patches=2048)
         return cfg, W.quadrants_blobs(2002), None
+    if name == "implosion":
+        # the paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2
+        cfg = W.AMRConfig(name="pimp", dim=2, base_cells=32, patch_cells=[16, 16, 16],
+                          periodic=[True, True], lo=-0.3, hi=0.3, cfl=0.45, ic="implosion",
+                          max_patches=2048)
+        return cfg, W.implosion(), None
     if name == "3d":
         cfg = W.AMRConfig(name="p3", dim=3, base_cells=32, patch_cells=[8, 8, 8],
                           periodic=[True] * 3, ic="blasts", max_patches=4096)

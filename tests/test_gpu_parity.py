@@ -18,7 +18,7 @@ from tests import _harness as H
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["1d", "2d", "2d-wall", "3d", "3d-uneven"]
+CASES = ["1d", "2d", "2d-wall", "implosion", "3d", "3d-uneven"]
 
 
 @pytest.fixture(scope="module")
@@ -138,7 +138,7 @@ def test_regrid_parity(name, amr):
         assert np.array_equal(H.interior(got[k], d), H.interior(o.U[0][k], d)), k
 
 
-@pytest.mark.parametrize("name", ["1d", "2d", "3d-uneven"])
+@pytest.mark.parametrize("name", ["1d", "2d", "implosion", "3d-uneven"])
 def test_lockstep_steps_with_regrid(name, amr):
     """Several steps with regrids every second step.  Both sides tag their own
     state; the request sets must agree (no decision within round-off of the
