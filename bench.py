@@ -212,6 +212,43 @@ def learned_gain(args) -> int:
     return 0
 
 
+def diag_bench(args) -> int:
+    """Time the velocity-gradient diagnostic (ghost fill of the leaves plus
+    the gradient kernel) on a workload's hierarchy after a few steps."""
+    import torch
+    from paper_2508_05020_amd import amr, workloads
+    cfg = workloads.config(args.config)
+    seed = args.seed
+    if seed is None:
+        num = args.config[1:] if args.config[:1] == "c" and args.config[1:].isdigit() else "2"
+        seed = workloads.seed_for(int(num), 1)
+    h = amr.Hierarchy(cfg)
+    amr.init_from_ic(h, workloads.initial_data(cfg, seed))
+    for _ in range(4):
+        h.step()
+    d = cfg.dim
+    out = torch.empty((d * d + 1, h.state_doubles // h.nvar), dtype=torch.float64, device=h.device)
+    for _ in range(args.warmup):
+        h._ok(amr._lib.amr_velocity_gradient(h.h, 0, h._ptr(out)))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    for _ in range(args.steps):
+        h._ok(amr._lib.amr_velocity_gradient(h.h, 0, h._ptr(out)))
+    e1.record(h.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    cells = h.leaf_cells()
+    # algorithmic bytes per leaf cell: (d + 1) values read, d*d + 1 written
+    b_cell = 8 * ((d + 1) + (d * d + 1))
+    print(json.dumps({"metric": "velocity-gradient diagnostic (fill + kernel) per call",
+                      "config": {"workload": cfg.name, "leaf_cells": cells},
+                      "ms_per_call": ms, "calls": args.steps,
+                      "bytes_per_cell": b_cell,
+                      "GBps_whole_call": cells * b_cell / ms / 1e6}), flush=True)
+    h.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +272,8 @@ def main() -> int:
     ap.add_argument("--learned-every", type=int, default=16,
                     help="regrid interval of the learned policy (and forecast horizon)")
     ap.add_argument("--learned-buffer", type=int, default=1, help="tag dilation in cells")
+    ap.add_argument("--diag", action="store_true",
+                    help="time the velocity-gradient diagnostic instead of the step")
     ap.add_argument("--learned-rounds", type=int, default=None,
                     help="predict + regrid rounds per learned regrid (each can add one level; "
                          "default 1 in 2D, 2 in 3D)")
@@ -251,6 +290,8 @@ def main() -> int:
         return copy_calibration()
     if args.learned:
         return learned_gain(args)
+    if args.diag:
+        return diag_bench(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is described in the design notes, not built.",

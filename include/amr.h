@@ -203,6 +203,20 @@ amr_status amr_fill_error(amr_hierarchy* h, int* flag);
 amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq,
                              amr_patch_info* out, int cap, int* n);
 
+/* Velocity-gradient diagnostic (the velocity-gradient task of the paper's
+ * fusion listing, §4.1, whose body the paper elides; the numerical Schlieren
+ * images of §5 are drawn from the density gradient).  Ghosts of the leaves
+ * of `buf` are filled first; then at every interior cell of every leaf
+ * patch, with u_i = m_i / rho and h the cell's level spacing:
+ *   G[i][j] = (u_i(x + h e_j) - u_i(x - h e_j)) / (2h)   (component i*d + j)
+ *   S = sqrt(sum_j ((rho(x + h e_j) - rho(x - h e_j)) / (2h))^2)  (component d*d)
+ * out_dev (caller-owned device memory) holds d*d + 1 planes of
+ * amr_state_doubles() / (d + 2) doubles each; a plane has the cell layout of
+ * one variable of the state buffer (a patch's (n+8)^d box starts at the
+ * patch's state offset divided by d + 2).  Only leaf interior cells are
+ * written.  Async on the hierarchy's stream. */
+amr_status amr_velocity_gradient(amr_hierarchy* h, int buf, double* out_dev);
+
 /* Number of leaf cells (sum of n_l^dim over leaf patches) of the current
  * mesh (no device work): the cells one step advances. */
 amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells);

@@ -17,6 +17,9 @@ Modules
   solver    -- the multi-level solver: ghost fill with conservative limited
                prolongation, restriction, refluxing, CFL time step, SSP-RK3
                stages, gradient tagging and regridding.
+  cnn       -- the learned refinement predictor (forward, backward, loss, Adam).
+  diagnostics -- velocity-gradient tensor and density-gradient magnitude
+               (numerical Schlieren) by central differences.
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 against closed forms, invariants or brute force, except where a function's

@@ -98,6 +98,7 @@ _sigs = {
     "amr_last_created": [_H, _P(C.c_int), C.c_int, _P(C.c_int)],
     "amr_fill_error": [_H, _P(C.c_int)],
     "amr_leaf_cells": [_H, _P(C.c_int64)],
+    "amr_velocity_gradient": [_H, C.c_int, C.c_void_p],
     "amr_profile": [_H, C.c_int],
     "amr_profile_read": [_H, _P(C.c_double), _P(C.c_int), _P(C.c_int64)],
     "amr_cnn_create": [_H, C.c_void_p, _P(_H)],
@@ -376,6 +377,16 @@ class Hierarchy:
         n = C.c_int()
         self._ok(_lib.amr_fill_error(self.h, C.byref(n)))
         return n.value
+
+    def velocity_gradient(self, buf: int = 0):
+        """Velocity-gradient tensor and density-gradient magnitude at leaf
+        interior cells: a device tensor [d*d + 1, state_doubles / nvar] in
+        the per-variable cell layout (NaN where nothing is written)."""
+        t = self.torch
+        out = t.full((self.cfg.dim ** 2 + 1, self.state_doubles // self.nvar), float("nan"),
+                     dtype=t.float64, device=self.device)
+        self._ok(_lib.amr_velocity_gradient(self.h, buf, self._ptr(out)))
+        return out
 
     def leaf_cells(self) -> int:
         n = C.c_int64()

@@ -13,6 +13,7 @@
 #include "amr_internal.hpp"
 #include "forest.hpp"
 #include "cnn_internal.hpp"
+#include "diag_internal.hpp"
 
 namespace {
 
@@ -1212,6 +1213,18 @@ amr_status amr_forest_replay(const amr_config* cfg, const int32_t* req, int nreq
   } catch (const std::exception&) {
     return AMR_E_ARG;
   }
+}
+
+amr_status amr_velocity_gradient(amr_hierarchy* h, int buf, double* out_dev) {
+  if (!h || !buf_ok(buf) || !out_dev) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    do_fill(h, buf, h->leaves);
+    const long long plane = h->state_doubles / h->nvar;
+    over_list(h, h->leaves, 1, [&](const int* p, int c) {
+      amr::Diagnostics::velocity_gradient(h->dm, h->U[buf], p, c, out_dev, plane, h->stream);
+    });
+    return AMR_OK;
+  });
 }
 
 amr_status amr_leaf_cells(const amr_hierarchy* h, int64_t* cells) {
