@@ -279,43 +279,73 @@ __global__ __launch_bounds__(NT) void k_reflux(DevMesh m, int mode, double* __re
 
 // Restriction of one child patch into the covered cells of its parent:
 // pairwise sums in x, then y, then z order, times 2^-D.
+// One covered parent cell (index idx of the h^D cells a child covers): the
+// pairwise sum of its 2^D child cells times 2^-D.
 template <int D>
-__device__ __forceinline__ void restrict_patch(const DevMesh& m, double* __restrict__ U,
-                                               int cpid) {
+__device__ __forceinline__ void restrict_cell(const DevMesh& m, double* __restrict__ U, int cpid,
+                                              int ppid, int lf, int h, int idx) {
   constexpr int NV = D + 2;
-  const int lf = m.level[cpid];
-  const int ppid = m.parent[cpid];
   const LevelC& F = m.lv[lf];
   const LevelC& C = m.lv[lf - 1];
-  const int h = F.n / 2;
   int o[3] = {0, 0, 0};
   for (int j = 0; j < D; ++j) o[j] = m.coord[3 * cpid + j] * h - m.coord[3 * ppid + j] * C.n;
   const double* Pc = U + patch_base(m, cpid, lf);
   double* Pp = U + patch_base(m, ppid, lf - 1);
   const long long vsf = var_stride<D>(F.full), vsc = var_stride<D>(C.full);
+  const int a = idx % h;
+  const int b = D >= 2 ? (idx / h) % h : 0;
+  const int c = D >= 3 ? idx / (h * h) : 0;
+  const long long dst = box_off<D>(C.full, o[0] + a + NG, o[1] + b + NG, o[2] + c + NG);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double* S = Pc + v * vsf;
+    auto at = [&](int x, int y, int z) {
+      return S[box_off<D>(F.full, 2 * a + x + NG, 2 * b + y + NG, 2 * c + z + NG)];
+    };
+    double r;
+    if constexpr (D == 1) r = (at(0, 0, 0) + at(1, 0, 0)) * 0.5;
+    else if constexpr (D == 2)
+      r = ((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) * 0.25;
+    else
+      r = (((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) +
+           ((at(0, 0, 1) + at(1, 0, 1)) + (at(0, 1, 1) + at(1, 1, 1)))) * 0.125;
+    Pp[v * vsc + dst] = r;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ int covered_cells(int h) {
   int total = h;
   if constexpr (D >= 2) total *= h;
   if constexpr (D >= 3) total *= h;
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int a = idx % h;
-    const int b = D >= 2 ? (idx / h) % h : 0;
-    const int c = D >= 3 ? idx / (h * h) : 0;
-    const long long dst = box_off<D>(C.full, o[0] + a + NG, o[1] + b + NG, o[2] + c + NG);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double* S = Pc + v * vsf;
-      auto at = [&](int x, int y, int z) {
-        return S[box_off<D>(F.full, 2 * a + x + NG, 2 * b + y + NG, 2 * c + z + NG)];
-      };
-      double r;
-      if constexpr (D == 1) r = (at(0, 0, 0) + at(1, 0, 0)) * 0.5;
-      else if constexpr (D == 2)
-        r = ((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) * 0.25;
-      else
-        r = (((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) +
-             ((at(0, 0, 1) + at(1, 0, 1)) + (at(0, 1, 1) + at(1, 1, 1)))) * 0.125;
-      Pp[v * vsc + dst] = r;
-    }
+  return total;
+}
+
+// restriction of patch cpid into its parent, by the whole block
+template <int D>
+__device__ __forceinline__ void restrict_patch(const DevMesh& m, double* __restrict__ U,
+                                               int cpid) {
+  const int lf = m.level[cpid];
+  const int ppid = m.parent[cpid];
+  const int h = m.lv[lf].n / 2;
+  const int total = covered_cells<D>(h);
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x)
+    restrict_cell<D>(m, U, cpid, ppid, lf, h, idx);
+}
+
+// restriction of every child of ppid into it, all children's covered cells in
+// one loop over the block (children share their level and edge)
+template <int D>
+__device__ __forceinline__ void restrict_children(const DevMesh& m, double* __restrict__ U,
+                                                  int ppid) {
+  const int nc = m.nchild[ppid];
+  if (nc <= 0) return;
+  const int lf = m.level[ppid] + 1;
+  const int h = m.lv[lf].n / 2;
+  const int per = covered_cells<D>(h);
+  for (int idx = threadIdx.x; idx < nc * per; idx += blockDim.x) {
+    const int k = idx / per;
+    restrict_cell<D>(m, U, m.child[(long long)ppid * m.maxc + k], ppid, lf, h, idx - k * per);
   }
 }
 
@@ -355,8 +385,7 @@ __global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode, double* __rest
     }
   } else if (b - nref < npair) {
     const int pid = plist[b - nref];
-    const int nc = m.nchild[pid];
-    for (int k = 0; k < nc; ++k) restrict_patch<D>(m, out, m.child[(long long)pid * m.maxc + k]);
+    restrict_children<D>(m, out, pid);
     if (lup >= 1) {
       __syncthreads();
       restrict_patch<D>(m, out, pid);
@@ -708,7 +737,7 @@ void Kernels::post(const DevMesh& m, int mode, double* out, const double* fr,
                                   lup, dt, w, lam_next)
   switch (m.dim) {
     case 1: AMR_POST(1, 64); break;
-    case 2: AMR_POST(2, 64); break;
+    case 2: AMR_POST(2, 256); break;
     default: AMR_POST(3, 256); break;
   }
 #undef AMR_POST
