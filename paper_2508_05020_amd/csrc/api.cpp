@@ -91,6 +91,7 @@ struct amr_hierarchy {
   // drains the stream, so earlier copies from it have completed)
   char* h_stage = nullptr;
   size_t h_stage_bytes = 0;
+  uint8_t* h_req = nullptr;  // pinned: refine and coarsen requests read back by amr_adapt
 
   // host mirrors of the work lists
   std::vector<int> lists;
@@ -144,6 +145,8 @@ struct amr_hierarchy {
     cap_stream = nullptr;
     if (h_stage) (void)hipHostFree(h_stage);
     h_stage = nullptr;
+    if (h_req) (void)hipHostFree(h_req);
+    h_req = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     for (void* p : owned) {
@@ -237,6 +240,10 @@ void build_devmesh(amr_hierarchy* h) {
 
 // Rebuild work lists on the host and upload them (plus the changed table
 // entries) to the device.
+// byte offset of the pinned flag slot in h_req (after 2 max_patches bytes of
+// requests, 64-byte aligned)
+size_t req_flag_offset(int mp) { return ((2 * (size_t)mp + 63) / 64) * 64; }
+
 void sync_tables(amr_hierarchy* h, bool full) {
   amr::Forest& f = h->forest;
   const int mp = f.max_patches;
@@ -584,10 +591,11 @@ void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_
 }
 
 int read_flag(amr_hierarchy* h, int idx) {
-  int v = 0;
-  HIP_OK(hipMemcpyAsync(&v, h->d_flags + idx, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  // through a pinned slot after the request buffers: an asynchronous copy
+  int* v = reinterpret_cast<int*>(h->h_req + req_flag_offset(h->forest.max_patches));
+  HIP_OK(hipMemcpyAsync(v, h->d_flags + idx, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   h->sync();
-  return v;
+  return *v;
 }
 
 void clear_flags(amr_hierarchy* h) {
@@ -726,6 +734,7 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->h_stage_bytes = (size_t)h->lists_cap * sizeof(int) + (size_t)h->pairs_cap * 2 * sizeof(int) +
                        2 * (size_t)mp + 256;
     HIP_OK(hipHostMalloc((void**)&h->h_stage, h->h_stage_bytes, hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h->h_req, req_flag_offset(mp) + 64, hipHostMallocDefault));
     HIP_OK(hipMemsetAsync(h->d_has_tag, 0, mp, h->stream));
     HIP_OK(hipMemsetAsync(h->fr, 0, h->fr_doubles * sizeof(double), h->stream));
     amr::DevMesh& m = h->dm;
@@ -1022,11 +1031,13 @@ amr_status amr_adapt(amr_hierarchy* h, int* ncreated, int* ndeleted) {
   return guarded(h, [&]() -> amr_status {
     const int mp = h->forest.max_patches;
     do_tag(h, 0, h->d_refine, h->d_coarsen, nullptr);
-    std::vector<uint8_t> rq(mp), cq(mp);
-    HIP_OK(hipMemcpyAsync(rq.data(), h->d_refine, mp, hipMemcpyDeviceToHost, h->stream));
-    HIP_OK(hipMemcpyAsync(cq.data(), h->d_coarsen, mp, hipMemcpyDeviceToHost, h->stream));
+    // into pinned memory: asynchronous copies, one wait
+    uint8_t* rq = h->h_req;
+    uint8_t* cq = h->h_req + mp;
+    HIP_OK(hipMemcpyAsync(rq, h->d_refine, mp, hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipMemcpyAsync(cq, h->d_coarsen, mp, hipMemcpyDeviceToHost, h->stream));
     h->sync();
-    return regrid_impl(h, rq.data(), cq.data(), ncreated, ndeleted);
+    return regrid_impl(h, rq, cq, ncreated, ndeleted);
   });
 }
 

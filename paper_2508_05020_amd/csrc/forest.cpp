@@ -387,6 +387,18 @@ int Forest::count_leaves() const {
 
 std::vector<int> Forest::sorted_active() const {
   std::vector<int> out;
+  // small level maps: their index order is (z, y, x) within a level, so a
+  // scan of the maps level by level yields the order without sorting
+  if (map.size() <= 4 * (size_t)max_patches) {
+    for (int l = 0; l < nlev; ++l) {
+      size_t cells = 1;
+      for (int j = 0; j < dim; ++j) cells *= (size_t)np[l];
+      const int* m = map.data() + map_off[l];
+      for (size_t i = 0; i < cells; ++i)
+        if (m[i] >= 0) out.push_back(m[i]);
+    }
+    return out;
+  }
   // (level, z, y, x, pid) packed into one 64-bit key when the fields fit
   // (level < 16, coordinates < 2^14, pid < 2^17), else the comparator
   bool packed = max_patches <= (1 << 17);
