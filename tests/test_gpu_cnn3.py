@@ -3,8 +3,6 @@ input gather bitwise; forward logits against the BF16-emulating reference;
 gradients against the FP64 reference backward; the Adam step; training
 lowers the loss; predicted requests on a mesh of 16^3 and 8^3 leaves, whose
 16^3 patches are predicted tile by tile."""
-import math
-
 import numpy as np
 import pytest
 
@@ -162,16 +160,29 @@ def test_training_lowers_loss(amr):
     assert last < 0.5 * first, (first, last)
 
 
-def test_predict_tiles_match_reference(amr):
+@pytest.mark.parametrize("case", ["3d-uneven", "3d-32"])
+def test_predict_tiles_match_reference(amr, case):
     """Requests from per-tile predictions on 16^3 (8 tiles) and 8^3 leaves,
-    small batches so that one patch's tiles span several launches."""
-    o, h, pid_of, key_of, pred, _ = _setup(amr, "3d-uneven", max_batch=5)
+    or 32^3 (64 tiles, the largest tile index) and 8^3 leaves, with small
+    batches so that one patch's tiles span several launches."""
+    if case == "3d-32":
+        from paper_2508_05020_amd import workloads as W
+        from oracle.solver import OracleAMR
+        cfg = W.AMRConfig(name="p32", dim=3, base_cells=64, patch_cells=[32, 8],
+                          periodic=[True] * 3, ic="blasts", max_patches=1024)
+        gen = W.blasts(3005, 3)
+        o = OracleAMR(cfg)
+        for k in o.forest.keys():
+            o.set_initial(k, gen)
+        o.regrid([(0, (1, 0, 1))], [], gen)
+        h = amr.Hierarchy(cfg)
+        pid_of, key_of = H.mirror(o, h)
+        pred = amr.Predictor(h, T, NORM_MEAN, NORM_STD, pos_weight=4.0, max_batch=7)
+    else:
+        o, h, pid_of, key_of, pred, _ = _setup(amr, case, max_batch=5)
     params = cnn.init_params(5, 8, 3, seed=25)
-    pred.set_weights(_flat(params))
-    wb = _params_from_flat(cnn.bf16_round(pred.get_weights()))
     o.fill_ghosts(0, o.forest.leaves())
-    # per-tile maximum logit of every leaf, from the oracle's state
-    tiles = {}
+    inputs = {}
     for k in o.forest.leaves():
         n = o.cfg.patch_cells[k[0]]
         U = o.U[0][k]
@@ -183,18 +194,25 @@ def test_predict_tiles_match_reference(amr):
                     a = U[:, T * tz + 1:T * tz + 1 + W0, T * ty + 1:T * ty + 1 + W0,
                           T * tx + 1:T * tx + 1 + W0]
                     xs.append(_tile_input(a, o.cfg.gamma).reshape(W0, W0, W0, 8)[..., :5])
-        xo = np.transpose(np.stack(xs), (0, 4, 1, 2, 3)).astype(np.float64)
-        z, _ = cnn.forward(xo, wb, bf16=True)
-        tiles[k] = z.reshape(len(xs), -1).max(axis=1)
+        inputs[k] = np.transpose(np.stack(xs), (0, 4, 1, 2, 3)).astype(np.float64)
+
+    def leaf_max_logits():
+        # the library's weights (BF16 copies of the weights, FP32 biases)
+        wb = _params_from_flat(pred.get_weights())
+        return {k: float(cnn.forward(x, wb, bf16=True)[0].max()) for k, x in inputs.items()}
+
     # a leaf is flagged when its largest tile logit exceeds the threshold;
-    # put the threshold in the widest gap between leaves' largest logits
-    lz = {k: float(z.max()) for k, z in tiles.items()}
-    vals = np.sort(np.array(list(lz.values())))
+    # put the threshold in the widest gap between leaves' largest logits and
+    # move it to logit 0 through the output bias (tau = 1/2)
+    pred.set_weights(_flat(params))
+    vals = np.sort(np.array(list(leaf_max_logits().values())))
     gaps = [(vals[i + 1] - vals[i], i) for i in range(1, len(vals) - 2)]
     _, gi = max(gaps)
-    zt = 0.5 * (vals[gi] + vals[gi + 1])
-    tau = 1.0 / (1.0 + math.exp(-zt))
-    zt32 = float(np.log(np.float32(tau) / (np.float32(1.0) - np.float32(tau))))
+    params[5] = np.array([-0.5 * (vals[gi] + vals[gi + 1])])
+    pred.set_weights(_flat(params))
+    lz = leaf_max_logits()
+    tau = 0.5
+    zt32 = 0.0
     margin = 2e-2 * float(np.max(np.abs(vals)))
     refine, coarsen = pred.predict(0, tau)
     refine = refine.cpu().numpy()
