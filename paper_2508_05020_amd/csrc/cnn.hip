@@ -224,7 +224,7 @@ __global__ void k_cnn_loss_final(const float* __restrict__ partial, int nblocks,
 // ---------------------------------------------------------------------------
 // backward of one patch per block: per-patch parameter-gradient partials
 // ---------------------------------------------------------------------------
-constexpr int BWD_THREADS = 256;
+constexpr int BWD_THREADS = 512;  // the loops stride over the block's waves
 
 __device__ __forceinline__ s4 pick4(const unsigned short* base, int stride) {
   s4 r;
@@ -241,18 +241,39 @@ __global__ __launch_bounds__(BWD_THREADS) void k_cnn_bwd(int count, int n,
                                                          const unsigned short* __restrict__ A2,
                                                          const float* __restrict__ G,
                                                          const unsigned short* __restrict__ Wb,
-                                                         float* __restrict__ partials) {
+                                                         float* __restrict__ partials,
+                                                         int stage_a1) {
   extern __shared__ unsigned short smem[];
   const int b = blockIdx.x;
   if (b >= count) return;
   const int w0 = n + 6, w1 = n + 4, w2 = n + 2;
   const int P0 = w0 * w0, P1 = w1 * w1, P2 = w2 * w2, P3 = n * n;
+  // the patch's input, second activation and logit gradients (and the first
+  // activation when LDS allows) are copied to LDS first, so that the
+  // reduction loops below read LDS
   unsigned short* dz2 = smem;            // P2 x 16
   unsigned short* dz1 = dz2 + P2 * 16;   // P1 x 16
-  const unsigned short* x = X + (long long)b * P0 * 4;
-  const unsigned short* a1 = A1 + (long long)b * P1 * 16;
-  const unsigned short* a2 = A2 + (long long)b * P2 * 16;
-  const float* g = G + (long long)b * P3;
+  unsigned short* sa2 = dz1 + P1 * 16;   // P2 x 16
+  unsigned short* sx = sa2 + P2 * 16;    // P0 x 4
+  float* sgr = reinterpret_cast<float*>(sx + P0 * 4);            // P3
+  unsigned short* sa1 = reinterpret_cast<unsigned short*>(sgr + P3);  // P1 x 16 (stage_a1)
+  const unsigned short* a1g = A1 + (long long)b * P1 * 16;
+  {
+    const uint4* g2 = reinterpret_cast<const uint4*>(A2 + (long long)b * P2 * 16);
+    const uint2* g0 = reinterpret_cast<const uint2*>(X + (long long)b * P0 * 4);
+    for (int t = threadIdx.x; t < P2 * 2; t += blockDim.x) reinterpret_cast<uint4*>(sa2)[t] = g2[t];
+    for (int t = threadIdx.x; t < P0; t += blockDim.x) reinterpret_cast<uint2*>(sx)[t] = g0[t];
+    for (int t = threadIdx.x; t < P3; t += blockDim.x) sgr[t] = G[(long long)b * P3 + t];
+    if (stage_a1) {
+      const uint4* g1 = reinterpret_cast<const uint4*>(a1g);
+      for (int t = threadIdx.x; t < P1 * 2; t += blockDim.x) reinterpret_cast<uint4*>(sa1)[t] = g1[t];
+    }
+  }
+  __syncthreads();
+  const unsigned short* x = sx;
+  const unsigned short* a1 = stage_a1 ? sa1 : a1g;
+  const unsigned short* a2 = sa2;
+  const float* g = sgr;
   float* part = partials + (long long)b * CNN_NPARAM;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -473,10 +494,19 @@ size_t Cnn::fwd_lds(int n) {
   return (size_t)(w0 * w0 * 4 + w1 * w1 * 16 + w2 * w2 * 16) * sizeof(unsigned short);
 }
 
-size_t Cnn::bwd_lds(int n) {
-  const int w1 = n + 4, w2 = n + 2;
-  return (size_t)(w1 * w1 * 16 + w2 * w2 * 16) * sizeof(unsigned short);
+// LDS of the backward kernel: dz2, dz1, a2, the input, the logit gradients,
+// and a1 when the total stays within the 160 KB of a CU
+static size_t bwd_lds_parts(int n, bool with_a1) {
+  const size_t P0 = (size_t)(n + 6) * (n + 6), P1 = (size_t)(n + 4) * (n + 4);
+  const size_t P2 = (size_t)(n + 2) * (n + 2), P3 = (size_t)n * n;
+  size_t bytes = (P2 * 16 + P1 * 16 + P2 * 16 + P0 * 4) * sizeof(unsigned short) + P3 * sizeof(float);
+  if (with_a1) bytes += P1 * 16 * sizeof(unsigned short);
+  return bytes;
 }
+
+static bool bwd_stage_a1(int n) { return bwd_lds_parts(n, true) <= 160 * 1024; }
+
+size_t Cnn::bwd_lds(int n) { return bwd_lds_parts(n, bwd_stage_a1(n)); }
 
 void Cnn::gather(const DevMesh& m, const double* U, const int* pids, int count, int n,
                  const CnnNorm& norm, unsigned short* X, hipStream_t s) {
@@ -518,7 +548,7 @@ void Cnn::backward(int count, int n, const unsigned short* X, const unsigned sho
   if (count <= 0) return;
   allow_large_lds();
   hipLaunchKernelGGL(k_cnn_bwd, dim3(count), dim3(BWD_THREADS), bwd_lds(n), s, count, n, X, A1, A2,
-                     G, Wb, partials);
+                     G, Wb, partials, bwd_stage_a1(n) ? 1 : 0);
   reduce(partials, count, CNN_NPARAM, grads, s);
 }
 

@@ -33,7 +33,10 @@ constexpr int CH = CNN3_CH;
 constexpr int W0 = T + 6, W1 = T + 4, W2 = T + 2;
 constexpr int P0 = CNN3_P0, P1 = CNN3_P1, P2 = CNN3_P2, P3 = CNN3_P3;
 constexpr int KCH = 14;  // K chunks: taps (2 kc, 2 kc + 1), 8 channels each
-constexpr int THREADS = 256;
+// threads per block: the loops stride over the block's waves, so more waves
+// shorten a tile's latency (a training batch is only tens of tiles)
+constexpr int FWD_THREADS = 512;
+constexpr int BWD_THREADS = 1024;
 
 static_assert(CH == 8, "two taps of 8 channels per MFMA K chunk");
 static_assert(P1 % 16 == 0, "layer-1 voxels in whole MFMA row blocks");
@@ -156,7 +159,7 @@ __device__ void conv3(const unsigned short* __restrict__ in, unsigned short* __r
   }
 }
 
-__global__ __launch_bounds__(THREADS) void k_cnn3_fwd(int count, const unsigned short* __restrict__ X,
+__global__ __launch_bounds__(FWD_THREADS) void k_cnn3_fwd(int count, const unsigned short* __restrict__ X,
                                                       const unsigned short* __restrict__ Wb,
                                                       const float* __restrict__ params,
                                                       unsigned short* __restrict__ A1,
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(THREADS) void k_cnn3_fwd(int count, const unsigned 
 // ---------------------------------------------------------------------------
 // backward of one tile per block: per-tile parameter-gradient partials
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(THREADS) void k_cnn3_bwd(int count, const unsigned short* __restrict__ X,
+__global__ __launch_bounds__(BWD_THREADS) void k_cnn3_bwd(int count, const unsigned short* __restrict__ X,
                                                       const unsigned short* __restrict__ A1,
                                                       const unsigned short* __restrict__ A2,
                                                       const float* __restrict__ G,
@@ -208,18 +211,28 @@ __global__ __launch_bounds__(THREADS) void k_cnn3_bwd(int count, const unsigned 
   extern __shared__ unsigned short smem[];
   const int b = blockIdx.x;
   if (b >= count) return;
+  // the tile's input and saved activations are copied to LDS first (one
+  // round of 16-byte loads), so that the reduction loops below read LDS
   unsigned short* dz2 = smem;              // P2 x 8
   unsigned short* dz1 = dz2 + P2 * CH;     // P1 x 8
-  float* sg = reinterpret_cast<float*>(dz1 + P1 * CH);  // P3 logit gradients
-  const unsigned short* x = X + (long long)b * P0 * CH;
-  const unsigned short* a1 = A1 + (long long)b * P1 * CH;
-  const unsigned short* a2 = A2 + (long long)b * P2 * CH;
+  unsigned short* a2 = dz1 + P1 * CH;      // P2 x 8
+  unsigned short* a1 = a2 + P2 * CH;       // P1 x 8
+  unsigned short* x = a1 + P1 * CH;        // P0 x 8
+  float* sg = reinterpret_cast<float*>(x + P0 * CH);  // P3 logit gradients
   float* part = partials + (long long)b * CNN3_NPARAM;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int half = kq >> 1, cg = 4 * (kq & 1);
 
+  {
+    const uint4* g2 = reinterpret_cast<const uint4*>(A2) + (long long)b * P2;
+    const uint4* g1 = reinterpret_cast<const uint4*>(A1) + (long long)b * P1;
+    const uint4* g0 = reinterpret_cast<const uint4*>(X) + (long long)b * P0;
+    for (int t = tid; t < P2; t += blockDim.x) reinterpret_cast<uint4*>(a2)[t] = g2[t];
+    for (int t = tid; t < P1; t += blockDim.x) reinterpret_cast<uint4*>(a1)[t] = g1[t];
+    for (int t = tid; t < P0; t += blockDim.x) reinterpret_cast<uint4*>(x)[t] = g0[t];
+  }
   for (int p = tid; p < P3; p += blockDim.x) sg[p] = G[(long long)b * P3 + p];
   __syncthreads();
 
@@ -400,7 +413,9 @@ __global__ __launch_bounds__(256) void k_cnn3_requests(int count, const float* _
 // ---------------------------------------------------------------------------
 size_t Cnn3::fwd_lds() { return (size_t)(P0 + P1) * CH * sizeof(unsigned short); }
 
-size_t Cnn3::bwd_lds() { return (size_t)(P2 + P1) * CH * sizeof(unsigned short) + P3 * sizeof(float); }
+size_t Cnn3::bwd_lds() {
+  return (size_t)(2 * P2 + 2 * P1 + P0) * CH * sizeof(unsigned short) + P3 * sizeof(float);
+}
 
 static void allow_large_lds3() {
   static bool done = false;
@@ -424,7 +439,7 @@ void Cnn3::forward(int count, const unsigned short* X, const unsigned short* Wb,
                    unsigned short* A1, unsigned short* A2, float* Z, hipStream_t s) {
   if (count <= 0) return;
   allow_large_lds3();
-  hipLaunchKernelGGL(k_cnn3_fwd, dim3(count), dim3(THREADS), fwd_lds(), s, count, X, Wb, params, A1,
+  hipLaunchKernelGGL(k_cnn3_fwd, dim3(count), dim3(FWD_THREADS), fwd_lds(), s, count, X, Wb, params, A1,
                      A2, Z);
 }
 
@@ -433,7 +448,7 @@ void Cnn3::backward(int count, const unsigned short* X, const unsigned short* A1
                     float* partials, float* grads, hipStream_t s) {
   if (count <= 0) return;
   allow_large_lds3();
-  hipLaunchKernelGGL(k_cnn3_bwd, dim3(count), dim3(THREADS), bwd_lds(), s, count, X, A1, A2, G, Wb,
+  hipLaunchKernelGGL(k_cnn3_bwd, dim3(count), dim3(BWD_THREADS), bwd_lds(), s, count, X, A1, A2, G, Wb,
                      partials);
   Cnn::reduce(partials, count, CNN3_NPARAM, grads, s);
 }
