@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <stdexcept>
 
 #include "amr_internal.hpp"
 
@@ -529,6 +530,37 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
   if constexpr (D >= 3) total *= w;
   int any = 0;
   uint8_t* rp = raw ? raw + L.tag_off + (long long)(pid - L.pid_base) * vs : nullptr;
+  if constexpr (D <= 2) {
+    // 1D/2D: rho and p of every node of the box [-b-1, n+b]^D once, in LDS
+    // (dynamic, sized for the largest patch edge), then the tests read LDS
+    extern __shared__ double stag[];
+    const int wn = w + 2;
+    const int nodes = D == 1 ? wn : wn * wn;
+    double* sr = stag;
+    double* sp = stag + nodes;
+    for (int idx = threadIdx.x; idx < nodes; idx += blockDim.x) {
+      const int c[3] = {idx % wn - b - 1, D >= 2 ? idx / wn - b - 1 : 0, 0};
+      rho_p_node<D, FUSE>(m, U, P, vs, L.full, n, l, pc, sN, c, sr[idx], sp[idx]);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+      const int c0 = idx % w - b, c1 = D >= 2 ? idx / w - b : 0;
+      const int node = (c0 + b + 1) + (D >= 2 ? (c1 + b + 1) * wn : 0);
+      bool t = false;
+      for (int j = 0; j < D; ++j) {
+        const int st = j == 0 ? 1 : wn;
+        const double rp_ = sr[node + st], rm_ = sr[node - st];
+        const double pp_ = sp[node + st], pm_ = sp[node - st];
+        t |= fabs(rp_ - rm_) > m.theta * (fabs(rp_) + fabs(rm_));
+        t |= fabs(pp_ - pm_) > m.theta * (fabs(pp_) + fabs(pm_));
+      }
+      any |= t;
+      if (rp) rp[box_off<D>(L.full, c0 + NG, c1 + NG, NG)] = t ? 1 : 0;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) has_tag[pid] = any ? 1 : 0;
+    return;
+  }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int c[3] = {idx % w - b, 0, 0};
     if constexpr (D >= 2) c[1] = (idx / w) % w - b;
@@ -769,10 +801,31 @@ void Kernels::dt_from_rate(const DevMesh& m, const unsigned long long* lam, doub
 void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,
                   uint8_t* has_tag, uint8_t* raw, bool fuse, hipStream_t s) {
   if (count <= 0) return;
+  // 1D/2D: LDS for rho and p on the largest patch's box [-b-1, n+b]^D
+  size_t lds = 0;
+  if (m.dim <= 2) {
+    int nmax = 0;
+    for (int l = 0; l < m.nlev; ++l) nmax = m.lv[l].n > nmax ? m.lv[l].n : nmax;
+    const size_t wn = (size_t)nmax + 2 * (size_t)m.tag_buffer + 2;
+    lds = 2 * (m.dim == 1 ? wn : wn * wn) * sizeof(double);
+    static bool big = false;
+    if (lds > 64 * 1024 && !big) {
+      big = true;
+      (void)hipFuncSetAttribute((const void*)k_tag<1, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_tag<1, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_tag<2, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipFuncSetAttribute((const void*)k_tag<2, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    }
+    if (lds > 160 * 1024) throw std::runtime_error("tagging box exceeds LDS");
+  }
 #define AMR_TAG(D)                                                                           \
   do {                                                                                       \
-    if (fuse) k_tag<D, true><<<count, 256, 0, s>>>(m, U, list, count, has_tag, raw);          \
-    else k_tag<D, false><<<count, 256, 0, s>>>(m, U, list, count, has_tag, raw);              \
+    if (fuse) k_tag<D, true><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw);        \
+    else k_tag<D, false><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw);            \
   } while (0)
   if (m.dim == 1) AMR_TAG(1);
   else if (m.dim == 2) AMR_TAG(2);
