@@ -252,7 +252,9 @@ def diag_bench(args) -> int:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the workload's configured run length, "
+                         "500 for C2; 128 for --learned; 50 calls for --diag)")
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--seed", type=int, default=None,
@@ -289,8 +291,12 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.learned:
+        if args.steps is None:
+            args.steps = 128
         return learned_gain(args)
     if args.diag:
+        if args.steps is None:
+            args.steps = 50
         return diag_bench(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -302,6 +308,8 @@ def main() -> int:
     from paper_2508_05020_amd import amr, workloads
 
     cfg = workloads.config(args.config)
+    if args.steps is None:
+        args.steps = cfg.steps
     if args.seed is None:
         num = args.config[1:] if args.config[:1] == "c" and args.config[1:].isdigit() else "2"
         args.seed = workloads.seed_for(int(num), 1)

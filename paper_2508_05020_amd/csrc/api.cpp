@@ -100,7 +100,10 @@ struct amr_hierarchy {
   amr::ListView post_pairs{}, post_singles{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
   std::vector<int> last_created;
-  std::vector<int8_t> parent_interior;  // scratch of sync_tables
+  // scratch of sync_tables, per parent: all Moore neighbours have children;
+  // bit mask (offset codes) of the Moore neighbours with children
+  std::vector<int8_t> parent_interior;
+  std::vector<int> parent_kids;
   std::vector<uint8_t> h_active_leaf;
   long long leaf_cells = 0;
 
@@ -329,20 +332,50 @@ void sync_tables(amr_hierarchy* h, bool full) {
     }
     return pint[P] == 1;
   };
+  // A leaf's same-level neighbour at offset src exists iff it is a sibling or
+  // the parent's Moore neighbour in that direction has children: children
+  // come in complete sets, and by R2 the parent has every Moore neighbour.
+  // So one mask per parent (bit = offset code of a neighbour with children)
+  // replaces the leaves' own neighbour lookups.
+  std::vector<int>& pkids = h->parent_kids;
+  pkids.assign(mp, -1);
+  auto kids_mask = [&](int P) {
+    if (pkids[P] < 0) {
+      const int lp = f.level[P];
+      const int cp[3] = {f.coord[3 * P], f.coord[3 * P + 1], f.coord[3 * P + 2]};
+      int bits = 0;
+      for (const auto& off : f.moore()) {
+        const int q = f.neighbour(lp, cp, off[0], off[1], off[2]);
+        if (q >= 0 && !f.is_leaf(q)) bits |= 1 << ((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
+      }
+      pkids[P] = bits;
+    }
+    return pkids[P];
+  };
   for (int pid : order) {
     if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
-    if (parent_interior(f.parent[pid])) continue;
+    const int P = f.parent[pid];
+    if (parent_interior(P)) continue;
     const int l = f.level[pid];
+    const int r = 2 * f.n[l - 1] / f.n[l];  // children per dimension
     const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
+    const int cpos[3] = {c[0] - f.coord[3 * P] * r, c[1] - f.coord[3 * P + 1] * r,
+                         c[2] - f.coord[3 * P + 2] * r};
+    const int kids = kids_mask(P);
     for (const auto& off : f.moore()) {
       int src[3] = {off[0], off[1], off[2]};
       bool self = true;
+      int dcode = 0, mul = 1;
       for (int j = 0; j < f.dim; ++j) {
         const int v = c[j] + src[j];
         if ((v < 0 || v >= f.np[l]) && !f.periodic[j]) src[j] = 0;
         self &= src[j] == 0;
+        const int w = cpos[j] + src[j];
+        dcode += ((w < 0) ? 0 : (w >= r ? 2 : 1)) * mul;
+        mul *= 3;
       }
-      if (self || f.neighbour(l, c, src[0], src[1], src[2]) != -1) continue;
+      if (f.dim < 3) dcode += (f.dim == 1 ? 12 : 9);  // centre index in the unused dimensions
+      if (self || dcode == 13 || ((kids >> dcode) & 1)) continue;
       L.push_back(pid);
       L.push_back((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
     }

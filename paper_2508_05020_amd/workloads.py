@@ -118,11 +118,12 @@ CONFIGS = {
                tag_buffer=2, ic="quadrants_blobs", max_patches=65536),
     # 3D blast waves + k^-2 density perturbations, base 256^3; each refined
     # 16^3 level-2 patch has 64 children of 8^3, so level 3 holds most of the
-    # ~175k patches (about 150 M leaf cells; the pools take ~170 GB).
+    # 175k-250k patches of a run (150-200 M leaf cells; the pools take about
+    # 200 GB).
     "c5": _cfg(name="c5", dim=3, base_cells=256, patch_cells=[32, 16, 16, 8],
                periodic=[True] * 3, steps=200, regrid_interval=8, tag_buffer=2,
-               ic="blasts_perturbed", max_patches=512 + 8192 + 16384 + 262144,
-               level_capacity=(512, 8192, 16384, 262144)),
+               ic="blasts_perturbed", max_patches=512 + 8192 + 16384 + 327680,
+               level_capacity=(512, 8192, 16384, 327680)),
     # The paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2.
     "implosion": _cfg(name="implosion", dim=2, base_cells=256,
                       patch_cells=[32, 16, 16], periodic=[True, True],
