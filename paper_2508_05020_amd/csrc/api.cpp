@@ -8,6 +8,7 @@
 #include <exception>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "amr_internal.hpp"
@@ -336,48 +337,67 @@ void sync_tables(amr_hierarchy* h, bool full) {
   // the parent's Moore neighbour in that direction has children: children
   // come in complete sets, and by R2 the parent has every Moore neighbour.
   // So one mask per parent (bit = offset code of a neighbour with children)
-  // replaces the leaves' own neighbour lookups.
+  // replaces the leaves' own neighbour lookups.  The parents' flags are set
+  // first; the leaves are then independent and, on large meshes, split over
+  // host threads whose parts are joined in order (the same list).
   std::vector<int>& pkids = h->parent_kids;
   pkids.assign(mp, -1);
-  auto kids_mask = [&](int P) {
-    if (pkids[P] < 0) {
-      const int lp = f.level[P];
-      const int cp[3] = {f.coord[3 * P], f.coord[3 * P + 1], f.coord[3 * P + 2]};
-      int bits = 0;
-      for (const auto& off : f.moore()) {
-        const int q = f.neighbour(lp, cp, off[0], off[1], off[2]);
-        if (q >= 0 && !f.is_leaf(q)) bits |= 1 << ((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
-      }
-      pkids[P] = bits;
-    }
-    return pkids[P];
-  };
-  for (int pid : order) {
-    if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
-    const int P = f.parent[pid];
-    if (parent_interior(P)) continue;
-    const int l = f.level[pid];
-    const int r = 2 * f.n[l - 1] / f.n[l];  // children per dimension
-    const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
-    const int cpos[3] = {c[0] - f.coord[3 * P] * r, c[1] - f.coord[3 * P + 1] * r,
-                         c[2] - f.coord[3 * P + 2] * r};
-    const int kids = kids_mask(P);
+  for (int P : order) {
+    if (f.is_leaf(P)) continue;
+    parent_interior(P);
+    const int lp = f.level[P];
+    const int cp[3] = {f.coord[3 * P], f.coord[3 * P + 1], f.coord[3 * P + 2]};
+    int bits = 0;
     for (const auto& off : f.moore()) {
-      int src[3] = {off[0], off[1], off[2]};
-      bool self = true;
-      int dcode = 0, mul = 1;
-      for (int j = 0; j < f.dim; ++j) {
-        const int v = c[j] + src[j];
-        if ((v < 0 || v >= f.np[l]) && !f.periodic[j]) src[j] = 0;
-        self &= src[j] == 0;
-        const int w = cpos[j] + src[j];
-        dcode += ((w < 0) ? 0 : (w >= r ? 2 : 1)) * mul;
-        mul *= 3;
+      const int q = f.neighbour(lp, cp, off[0], off[1], off[2]);
+      if (q >= 0 && !f.is_leaf(q)) bits |= 1 << ((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
+    }
+    pkids[P] = bits;
+  }
+  auto regions = [&](size_t lo, size_t hi, std::vector<int>& out) {
+    for (size_t i = lo; i < hi; ++i) {
+      const int pid = order[i];
+      if (!f.is_leaf(pid) || f.level[pid] == 0) continue;
+      const int P = f.parent[pid];
+      if (pint[P] == 1) continue;
+      const int l = f.level[pid];
+      const int r = 2 * f.n[l - 1] / f.n[l];  // children per dimension
+      const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
+      const int cpos[3] = {c[0] - f.coord[3 * P] * r, c[1] - f.coord[3 * P + 1] * r,
+                           c[2] - f.coord[3 * P + 2] * r};
+      const int kids = pkids[P];
+      for (const auto& off : f.moore()) {
+        int src[3] = {off[0], off[1], off[2]};
+        bool self = true;
+        int dcode = 0, mul = 1;
+        for (int j = 0; j < f.dim; ++j) {
+          const int v = c[j] + src[j];
+          if ((v < 0 || v >= f.np[l]) && !f.periodic[j]) src[j] = 0;
+          self &= src[j] == 0;
+          const int w = cpos[j] + src[j];
+          dcode += ((w < 0) ? 0 : (w >= r ? 2 : 1)) * mul;
+          mul *= 3;
+        }
+        if (f.dim < 3) dcode += (f.dim == 1 ? 12 : 9);  // centre index of the unused dimensions
+        if (self || dcode == 13 || ((kids >> dcode) & 1)) continue;
+        out.push_back(pid);
+        out.push_back((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
       }
-      if (f.dim < 3) dcode += (f.dim == 1 ? 12 : 9);  // centre index in the unused dimensions
-      if (self || dcode == 13 || ((kids >> dcode) & 1)) continue;
-      L.push_back(pid);
-      L.push_back((off[0] + 1) + 3 * (off[1] + 1) + 9 * (off[2] + 1));
+    }
+  };
+  {
+    const size_t na = order.size();
+    unsigned nth = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (na < 16384) nth = 1;
+    if (nth == 1) {
+      regions(0, na, L);
+    } else {
+      std::vector<std::vector<int>> parts(nth);
+      std::vector<std::thread> pool;
+      for (unsigned t = 0; t < nth; ++t)
+        pool.emplace_back(regions, na * t / nth, na * (t + 1) / nth, std::ref(parts[t]));
+      for (auto& th : pool) th.join();
+      for (const auto& part : parts) L.insert(L.end(), part.begin(), part.end());
     }
   }
   // coarsening candidates: patches whose children are all leaves
