@@ -495,7 +495,7 @@ template <int D, bool FUSE>
 __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict__ U,
                                              const int* __restrict__ list, int count,
                                              uint8_t* __restrict__ has_tag,
-                                             uint8_t* __restrict__ raw) {
+                                             uint8_t* __restrict__ raw, int lds_nodes) {
   if ((int)blockIdx.x >= count) return;
   const int pid = list[blockIdx.x];
   const int l = m.level[pid];
@@ -530,32 +530,40 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
   if constexpr (D >= 3) total *= w;
   int any = 0;
   uint8_t* rp = raw ? raw + L.tag_off + (long long)(pid - L.pid_base) * vs : nullptr;
-  if constexpr (D <= 2) {
-    // 1D/2D: rho and p of every node of the box [-b-1, n+b]^D once, in LDS
-    // (dynamic, sized for the largest patch edge), then the tests read LDS
+  // rho and p of every node of the box [-b-1, n+b]^D once, in LDS (dynamic,
+  // sized on the host for the largest patch edge whose box fits; always in
+  // 1D/2D), then the tests read LDS; larger 3D patches compute each cell's
+  // neighbours directly below
+  const int wn = w + 2;
+  int nodes = wn;
+  if constexpr (D >= 2) nodes *= wn;
+  if constexpr (D >= 3) nodes *= wn;
+  if (nodes <= lds_nodes) {
     extern __shared__ double stag[];
-    const int wn = w + 2;
-    const int nodes = D == 1 ? wn : wn * wn;
     double* sr = stag;
     double* sp = stag + nodes;
     for (int idx = threadIdx.x; idx < nodes; idx += blockDim.x) {
-      const int c[3] = {idx % wn - b - 1, D >= 2 ? idx / wn - b - 1 : 0, 0};
+      const int c[3] = {idx % wn - b - 1, D >= 2 ? (idx / wn) % wn - b - 1 : 0,
+                        D >= 3 ? idx / (wn * wn) - b - 1 : 0};
       rho_p_node<D, FUSE>(m, U, P, vs, L.full, n, l, pc, sN, c, sr[idx], sp[idx]);
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-      const int c0 = idx % w - b, c1 = D >= 2 ? idx / w - b : 0;
-      const int node = (c0 + b + 1) + (D >= 2 ? (c1 + b + 1) * wn : 0);
+      const int c0 = idx % w - b;
+      const int c1 = D >= 2 ? (idx / w) % w - b : 0;
+      const int c2 = D >= 3 ? idx / (w * w) - b : 0;
+      const int node = (c0 + b + 1) + (D >= 2 ? (c1 + b + 1) * wn : 0) +
+                       (D >= 3 ? (c2 + b + 1) * wn * wn : 0);
       bool t = false;
       for (int j = 0; j < D; ++j) {
-        const int st = j == 0 ? 1 : wn;
+        const int st = j == 0 ? 1 : (j == 1 ? wn : wn * wn);
         const double rp_ = sr[node + st], rm_ = sr[node - st];
         const double pp_ = sp[node + st], pm_ = sp[node - st];
         t |= fabs(rp_ - rm_) > m.theta * (fabs(rp_) + fabs(rm_));
         t |= fabs(pp_ - pm_) > m.theta * (fabs(pp_) + fabs(pm_));
       }
       any |= t;
-      if (rp) rp[box_off<D>(L.full, c0 + NG, c1 + NG, NG)] = t ? 1 : 0;
+      if (rp) rp[box_off<D>(L.full, c0 + NG, c1 + NG, c2 + NG)] = t ? 1 : 0;
     }
     any = __syncthreads_or(any);
     if (threadIdx.x == 0) has_tag[pid] = any ? 1 : 0;
@@ -801,15 +809,20 @@ void Kernels::dt_from_rate(const DevMesh& m, const unsigned long long* lam, doub
 void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,
                   uint8_t* has_tag, uint8_t* raw, bool fuse, hipStream_t s) {
   if (count <= 0) return;
-  // 1D/2D: LDS for rho and p on the largest patch's box [-b-1, n+b]^D
-  size_t lds = 0;
-  if (m.dim <= 2) {
-    int nmax = 0;
-    for (int l = 0; l < m.nlev; ++l) nmax = m.lv[l].n > nmax ? m.lv[l].n : nmax;
-    const size_t wn = (size_t)nmax + 2 * (size_t)m.tag_buffer + 2;
-    lds = 2 * (m.dim == 1 ? wn : wn * wn) * sizeof(double);
+  // LDS for rho and p on the box [-b-1, n+b]^D of the largest patch edge
+  // (1D/2D), or of the largest edge whose box fits 64 KB (3D)
+  int lds_nodes = 0;
+  for (int l = 0; l < m.nlev; ++l) {
+    const long long wn = (long long)m.lv[l].n + 2 * m.tag_buffer + 2;
+    const long long nodes = m.dim == 1 ? wn : (m.dim == 2 ? wn * wn : wn * wn * wn);
+    if (m.dim <= 2 || nodes * 2 * (long long)sizeof(double) <= 64 * 1024)
+      lds_nodes = std::max<long long>(lds_nodes, nodes);
+  }
+  const size_t lds = 2 * (size_t)lds_nodes * sizeof(double);
+  if (lds > 160 * 1024) throw std::runtime_error("tagging box exceeds LDS");
+  if (lds > 64 * 1024) {
     static bool big = false;
-    if (lds > 64 * 1024 && !big) {
+    if (!big) {
       big = true;
       (void)hipFuncSetAttribute((const void*)k_tag<1, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -820,12 +833,11 @@ void Kernels::tag(const DevMesh& m, const double* U, const int* list, int count,
       (void)hipFuncSetAttribute((const void*)k_tag<2, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     }
-    if (lds > 160 * 1024) throw std::runtime_error("tagging box exceeds LDS");
   }
 #define AMR_TAG(D)                                                                           \
   do {                                                                                       \
-    if (fuse) k_tag<D, true><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw);        \
-    else k_tag<D, false><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw);            \
+    if (fuse) k_tag<D, true><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw, lds_nodes); \
+    else k_tag<D, false><<<count, 256, lds, s>>>(m, U, list, count, has_tag, raw, lds_nodes);    \
   } while (0)
   if (m.dim == 1) AMR_TAG(1);
   else if (m.dim == 2) AMR_TAG(2);
