@@ -229,11 +229,11 @@ def diag_bench(args) -> int:
     d = cfg.dim
     out = torch.empty((d * d + 1, h.state_doubles // h.nvar), dtype=torch.float64, device=h.device)
     for _ in range(args.warmup):
-        h._ok(amr._lib.amr_velocity_gradient(h.h, 0, h._ptr(out)))
+        h.velocity_gradient(0, out)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(h.stream)
     for _ in range(args.steps):
-        h._ok(amr._lib.amr_velocity_gradient(h.h, 0, h._ptr(out)))
+        h.velocity_gradient(0, out)
     e1.record(h.stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / args.steps

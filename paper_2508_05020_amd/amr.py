@@ -378,13 +378,17 @@ class Hierarchy:
         self._ok(_lib.amr_fill_error(self.h, C.byref(n)))
         return n.value
 
-    def velocity_gradient(self, buf: int = 0):
+    def velocity_gradient(self, buf: int = 0, out=None):
         """Velocity-gradient tensor and density-gradient magnitude at leaf
         interior cells: a device tensor [d*d + 1, state_doubles / nvar] in
-        the per-variable cell layout (NaN where nothing is written)."""
+        the per-variable cell layout (a new one filled with NaN where nothing
+        is written, or ``out``, which is reused as it is)."""
         t = self.torch
-        out = t.full((self.cfg.dim ** 2 + 1, self.state_doubles // self.nvar), float("nan"),
-                     dtype=t.float64, device=self.device)
+        shape = (self.cfg.dim ** 2 + 1, self.state_doubles // self.nvar)
+        if out is None:
+            out = t.full(shape, float("nan"), dtype=t.float64, device=self.device)
+        elif tuple(out.shape) != shape or out.dtype != t.float64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor of shape {shape}")
         self._ok(_lib.amr_velocity_gradient(self.h, buf, self._ptr(out)))
         return out
 
