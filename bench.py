@@ -254,7 +254,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's configured run length, "
-                         "500 for C2; 128 for --learned; 50 calls for --diag)")
+                         "500 for c2; 128 for --learned; 50 calls for --diag)")
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--seed", type=int, default=None,

@@ -7,7 +7,7 @@ of 3 cells) to a per-cell logit of "this cell will be tagged within the next
 k steps".  Three valid 3x3 (2D) or 3x3x3 (3D) convolutions with bias, ReLU
 after the first two, sigmoid on the output:
 
-    x [C0, n+6, ...] -> conv1 -> relu -> [C1, n+4] -> conv2 -> relu -> [C1, n+2]
+    x [cin, n+6, ...] -> conv1 -> relu -> [ch, n+4] -> conv2 -> relu -> [ch, n+2]
       -> conv3 -> [1, n] logits
 
 Loss: binary cross-entropy with logits and a positive-class weight,

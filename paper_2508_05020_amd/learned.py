@@ -40,8 +40,8 @@ def net_shape(dim: int):
 
 def init_weights(seed: int, dim: int = 2) -> np.ndarray:
     """He-normal weights, zero biases, in the flat parameter layout of the
-    library: W1 [C1][C0][taps], b1, W2 [C1][C1][taps], b2, W3 [C1][taps], b3
-    with (C0, C1, taps) = (4, 16, 3x3) in 2D and (5, 8, 3x3x3) in 3D."""
+    library: W1 [ch][cin][taps], b1, W2 [ch][ch][taps], b2, W3 [ch][taps], b3
+    with (cin, ch, taps) = (4, 16, 3x3) in 2D and (5, 8, 3x3x3) in 3D."""
     c0, c1, k = net_shape(dim)
     rng = np.random.default_rng(seed)
     parts = [rng.normal(0.0, math.sqrt(2.0 / (c0 * k)), c1 * c0 * k), np.zeros(c1),

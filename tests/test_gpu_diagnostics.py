@@ -1,7 +1,7 @@
 """Velocity-gradient diagnostic of the library against the oracle (GPU):
 every component at every leaf interior cell, 1e-12 relative L-infinity per
 component, on meshes with coarse/fine ghosts, periodic and transmissive
-boundaries, and on the full-size C2 hierarchy."""
+boundaries, and on the full-size c2 hierarchy (2D, 256^2 base, 3 levels)."""
 import numpy as np
 import pytest
 
@@ -37,7 +37,7 @@ def test_velocity_gradient_parity(name, amr):
 
 
 def test_velocity_gradient_full_size_c2(amr):
-    """The C2 workload (256^2 base, 3 levels, quadrants + blobs) after one
+    """The c2 workload (2D, 256^2 base, 3 levels, quadrants + blobs) after one
     step: every component at every leaf interior cell."""
     from oracle.solver import OracleAMR
     from paper_2508_05020_amd import workloads as W

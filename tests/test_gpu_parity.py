@@ -257,7 +257,7 @@ def test_conservation_gpu(amr):
 
 
 def test_full_size_c2_one_step(amr):
-    """The benchmark workload (C2: 256^2 base, 3 levels) in the benchmark's
+    """The benchmark workload (c2: 2D, 256^2 base, 3 levels) in the benchmark's
     launch configuration: every leaf cell after one step."""
     cfg = W.config("c2")
     o = OracleAMR(cfg)
