@@ -161,15 +161,27 @@ def learned_gain(args) -> int:
     log(f"[learned] {data.x.shape[0]} training tiles from {len(seeds)} runs at {res}, "
         f"positive cells {pos:.3f} ({time.perf_counter() - t0:.1f} s)")
 
-    def hier(mode=amr.EXEC_BATCHED):
-        h = amr.Hierarchy(cfg, exec_mode=mode)
-        amr.init_from_ic(h, workloads.initial_data(cfg, seed_eval))
+    # evaluation workload: the training configuration, or a named one (its
+    # dilation set to the one the labels were made with)
+    ecfg, eseed = cfg, seed_eval
+    if args.learned_eval:
+        ecfg = workloads.config(args.learned_eval).replace(tag_buffer=b)
+        if ecfg.dim != dim:
+            raise SystemExit(f"--learned-eval {args.learned_eval} is {ecfg.dim}D, the network {dim}D")
+        num = args.learned_eval[1:] if args.learned_eval[1:].isdigit() else "0"
+        eseed = workloads.seed_for(int(num), 1)
+
+    def hier(mode=amr.EXEC_BATCHED, c=None, seed=None):
+        c = ecfg if c is None else c
+        h = amr.Hierarchy(c, exec_mode=mode)
+        amr.init_from_ic(h, workloads.initial_data(c, eseed if seed is None else seed))
         return h
 
-    h = hier()
-    learned.run_policy(h, 8, 2, "plain", judge=True)  # warm-up outside the comparison
-    h.close()
-    h_bl = hier()
+    if not args.learned_eval:
+        h = hier()
+        learned.run_policy(h, 8, 2, "plain", judge=True)  # warm-up outside the comparison
+        h.close()
+    h_bl = hier() if not args.learned_eval else hier(c=cfg, seed=seed_eval)
     pred = amr.Predictor(h_bl, n, mean, std, pos_weight=pos_weight, max_batch=256)
     pred.set_weights(learned.init_weights(seed=1, dim=dim))
     t1 = time.perf_counter()
@@ -181,30 +193,54 @@ def learned_gain(args) -> int:
     log(f"[learned] trained in {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
         f"tau {tau:.4f}, validation {met}")
 
+    if args.learned_eval:
+        # the evaluation hierarchy gets its own predictor with the trained
+        # weights; one large hierarchy at a time
+        weights = pred.get_weights()
+        pred.close()
+        h_bl.close()
+        import torch
+        torch.cuda.empty_cache()
+
     results = {}
     steps = args.steps
     for name, every, policy, mode in (("plain2_per_patch", 2, "plain", amr.EXEC_PER_PATCH),
                                       ("plain2", 2, "plain", amr.EXEC_BATCHED),
                                       (f"plain{H}", H, "plain", amr.EXEC_BATCHED),
                                       (f"learned{H}", H, "learned", amr.EXEC_BATCHED)):
-        h = h_bl if policy == "learned" else hier(mode)
+        if args.learned_eval and mode == amr.EXEC_PER_PATCH:
+            continue  # one launch per patch and phase: hours on a large workload
+        if policy == "learned" and args.learned_eval:
+            h = hier()
+            pred = amr.Predictor(h, n, mean, std, pos_weight=pos_weight, max_batch=256)
+            pred.set_weights(weights)
+            pred.predict(0, tau)
+        else:
+            h = h_bl if policy == "learned" else hier(mode)
         st = learned.run_policy(h, steps, every, policy, pred if policy == "learned" else None,
                                 tau, judge=True, rounds=rounds)
         results[name] = st.as_dict()
         log(f"[learned] {name}: {results[name]}")
         if policy != "learned":
             h.close()
+            if args.learned_eval:
+                import torch
+                torch.cuda.empty_cache()
     L = results[f"learned{H}"]["wall_per_tsim"]
+    desc = (f"{ecfg.name}: {dim}D base {ecfg.base_cells}^{dim}, {ecfg.max_levels} levels of "
+            f"{ecfg.patch_cells} patches, dilation {b}, seed {eseed}, {steps} steps")
+    if args.learned_eval:
+        desc += (f"; network trained on {cfg.name} ({dim}D base {cfg.base_cells}^{dim}, "
+                 f"{n}^{dim} patches)")
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
-           "config": {"workload": f"{cfg.name}: {dim}D base {cfg.base_cells}^{dim}, {cfg.max_levels} "
-                                  f"levels of {n}^{dim} patches, dilation {b}, seed {seed_eval}, "
-                                  f"{steps} steps"},
+           "config": {"workload": desc},
            "learned_rounds": rounds,
            "training": {"tiles": int(data.x.shape[0]), "runs": len(seeds), "horizon": H,
                         "epochs": args.epochs, "first_loss": losses[0], "final_loss": losses[-1],
                         "seconds": train_s, "tau": tau, "validation": met},
            "policies": results,
-           "gain_vs_plain2_per_patch": results["plain2_per_patch"]["wall_per_tsim"] / L,
+           "gain_vs_plain2_per_patch": (results["plain2_per_patch"]["wall_per_tsim"] / L
+                                        if "plain2_per_patch" in results else None),
            "gain_vs_plain2": results["plain2"]["wall_per_tsim"] / L,
            f"gain_vs_plain{H}": results[f"plain{H}"]["wall_per_tsim"] / L}
     print(json.dumps(out), flush=True)
@@ -279,6 +315,9 @@ def main() -> int:
     ap.add_argument("--learned-rounds", type=int, default=None,
                     help="predict + regrid rounds per learned regrid (each can add one level; "
                          "default 1 in 2D, 2 in 3D)")
+    ap.add_argument("--learned-eval", default=None,
+                    help="evaluate the policies on this workload (e.g. c5) instead of the "
+                         "training configuration; per-patch launches are skipped there")
     ap.add_argument("--learned-dim", type=int, default=2, choices=[2, 3],
                     help="2D quadrants + blobs or 3D blast waves + perturbations")
     ap.add_argument("--seed-eval", type=int, default=None,
