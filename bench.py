@@ -135,8 +135,15 @@ def learned_gain(args) -> int:
     seed_eval = args.seed_eval if args.seed_eval is not None else (4100 if dim == 2 else 5100)
     rounds = args.learned_rounds if args.learned_rounds is not None else (1 if dim == 2 else 2)
     if dim == 2:
+        # the patch edge of the evaluation workload when one is named (the 2D
+        # network predicts leaves of one edge), else 16
         n = 16
-        cfg = workloads.AMRConfig(name="quadrants-blobs-4lev", dim=2, base_cells=64,
+        if args.learned_eval:
+            edges = set(workloads.config(args.learned_eval).patch_cells)
+            if len(edges) != 1:
+                raise SystemExit("the 2D network needs one patch edge on every level")
+            n = edges.pop()
+        cfg = workloads.AMRConfig(name="quadrants-blobs-4lev", dim=2, base_cells=max(64, 2 * n),
                                   patch_cells=[n] * 4, periodic=[True, True],
                                   ic="quadrants_blobs", tag_buffer=b, max_patches=16384)
         seeds = list(range(4000, 4000 + args.train_runs))
