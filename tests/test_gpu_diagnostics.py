@@ -68,3 +68,18 @@ def _compare(h, o, pid_of, d):
     assert np.all(num[den == 0] == 0), (num, den)
     err = float(np.max(num / np.where(den > 0, den, 1.0)))
     assert err <= H.TOL, (num, den)
+
+
+def test_velocity_gradient_into_a_given_tensor(amr):
+    """A caller's output tensor is filled in place (same values as a fresh
+    one) and one of the wrong shape is refused before any device work."""
+    import torch
+    o, h, pid_of, key_of = H.mirror_case("2d", amr)
+    ref = h.velocity_gradient(0)
+    out = torch.zeros_like(ref)
+    got = h.velocity_gradient(0, out)
+    assert got.data_ptr() == out.data_ptr()
+    leaf = torch.isfinite(ref)
+    assert torch.equal(out[leaf], ref[leaf])
+    with pytest.raises(ValueError):
+        h.velocity_gradient(0, torch.zeros(3, 5, dtype=torch.float64, device=ref.device))
