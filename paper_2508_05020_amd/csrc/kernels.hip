@@ -741,7 +741,8 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
   if (count <= 0) return;
   switch (m.dim) {
     case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
-    case 2: k_fill_cf<2, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
+    // a side region of a 32^2 patch is 128 cells: one cell per thread
+    case 2: k_fill_cf<2, 128><<<count, 128, 0, s>>>(m, U, list, count, err); break;
     default: k_fill_cf<3, 256><<<count, 256, 0, s>>>(m, U, list, count, err); break;
   }
 }
