@@ -741,8 +741,17 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
   if (count <= 0) return;
   switch (m.dim) {
     case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
-    // a side region of a 32^2 patch is 128 cells: one cell per thread
-    case 2: k_fill_cf<2, 128><<<count, 128, 0, s>>>(m, U, list, count, err); break;
+    case 2: {
+      // one cell per thread: a side region is 4 n cells (64 at n = 16, 128 at
+      // n = 32); level 0 has no prolonged ghosts
+      int nmax = 0;
+      for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
+      if (nmax <= 16)
+        k_fill_cf<2, 64><<<count, 64, 0, s>>>(m, U, list, count, err);
+      else
+        k_fill_cf<2, 128><<<count, 128, 0, s>>>(m, U, list, count, err);
+      break;
+    }
     default: k_fill_cf<3, 256><<<count, 256, 0, s>>>(m, U, list, count, err); break;
   }
 }
