@@ -411,7 +411,22 @@ std::vector<int> Forest::sorted_active() const {
                      ((uint64_t)coord[3 * pid + 1] << 31) | ((uint64_t)coord[3 * pid] << 17) |
                      (uint64_t)pid);
     }
-    std::sort(keys.begin(), keys.end());
+    if (keys.size() < 4096) {
+      std::sort(keys.begin(), keys.end());
+    } else {
+      // LSD radix sort on the 46 ordering bits above the pid field (17..62),
+      // three 16-bit digits; the keys are distinct, so the order is the
+      // comparison sort's
+      std::vector<uint64_t> tmp(keys.size());
+      std::vector<uint32_t> cnt(65537);
+      for (const int sh : {17, 33, 49}) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (const uint64_t k : keys) ++cnt[((k >> sh) & 0xffffu) + 1];
+        for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+        for (const uint64_t k : keys) tmp[cnt[(k >> sh) & 0xffffu]++] = k;
+        keys.swap(tmp);
+      }
+    }
     out.reserve(keys.size());
     for (uint64_t k : keys) out.push_back((int)(k & ((1u << 17) - 1)));
     return out;

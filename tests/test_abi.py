@@ -101,3 +101,26 @@ def test_forest_replay_capacity_error():
     with pytest.raises(A.AMRError) as e:
         A.forest_replay(cfg, [([(0, (0, 0)), (0, (2, 2)), (0, (0, 2))], [])])
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("dim,base,nrefine", [(2, 1024, 300), (3, 256, 80)])
+def test_forest_replay_order_large(dim, base, nrefine):
+    """Active patches come out in (level, z, y, x) order from both host
+    paths: the level-map scan (capacity large against the maps) and the
+    packed-key radix sort (capacity small against the maps, >= 4096 keys)."""
+    A = _lib()
+    rnd = random.Random(dim)
+    np0 = base // 16
+    coords = [tuple(rnd.randrange(np0) for _ in range(dim)) for _ in range(nrefine)]
+    nsub, c0 = nrefine * 2 // 5, nrefine * 2 // 3
+    rounds = [([(0, c) for c in coords], []),
+              ([(1, tuple(2 * x + rnd.randrange(2) for x in c)) for c in coords[:nsub]], []),
+              ([], [(0, c) for c in coords[c0:c0 + nrefine // 5]])]
+    outs = []
+    for mp in ((9000 if dim == 2 else 20000), 400000):
+        cfg = W.AMRConfig(name="m", dim=dim, base_cells=base, patch_cells=[16, 16, 16],
+                          periodic=[True] * dim, max_patches=mp)
+        outs.append([(r[0], r[1], r[3]) for r in A.forest_replay(cfg, rounds)])
+    assert len(outs[0]) > 4096
+    assert outs[0] == outs[1]
+    assert outs[0] == sorted(outs[0], key=lambda r: (r[0], r[1][::-1]))
