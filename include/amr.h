@@ -124,9 +124,14 @@ amr_status amr_get_patch_table(const amr_hierarchy* h, amr_patch_info* out, int 
 
 /* Upload / download whole patch arrays (ghosts included) for `npatch` pids;
  * the host buffer is the concatenation of the patches' arrays in `pids`
- * order (sync).  amr_set_state_prim takes interior primitive values
- * (rho, u_x[, u_y[, u_z]], p), var-major over n_l^dim cells per patch, and
- * stores E = p / (gamma - 1) + rho u.u / 2 (Eq. (4), (6)). */
+ * order (sync); patches adjacent in their level's pool move in one copy.
+ * amr_set_state_prim takes interior primitive values (rho, u_x[, u_y[,
+ * u_z]], p), var-major over n_l^dim cells per patch, converts them on the
+ * device to rho, rho u and E = p / (gamma - 1) + rho u.u / 2 (Eq. (4), (6))
+ * and leaves ghost cells as they are; it stages the values through a device
+ * buffer of at most 128 MiB (or one patch), taken from the hierarchy's
+ * allocator and returned before it returns.  Each pid appears at most
+ * once.  An inactive pid is AMR_E_ARG, found before anything is written. */
 amr_status amr_set_state(amr_hierarchy* h, int buf, const double* host, const int* pids, int npatch);
 amr_status amr_get_state(const amr_hierarchy* h, int buf, double* host, const int* pids, int npatch);
 amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* host_prim,

@@ -15,6 +15,7 @@
 #include "forest.hpp"
 #include "cnn_internal.hpp"
 #include "diag_internal.hpp"
+#include "state_io_internal.hpp"
 
 namespace {
 
@@ -140,6 +141,14 @@ struct amr_hierarchy {
     owned.push_back(p);
     return p;
   }
+  // frees one allocation made by dev_alloc before the hierarchy ends
+  void dev_free(void* p) {
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it == owned.end()) return;
+    owned.erase(it);
+    if (has_alloc) alloc.free(p, alloc.ctx);
+    else (void)hipFree(p);
+  }
   void release_all() {
     for (int k = 0; k < 2; ++k) {
       if (step_exec[k]) (void)hipGraphExecDestroy(step_exec[k]);
@@ -171,6 +180,35 @@ int ipow(int b, int e) {
   int r = 1;
   for (int i = 0; i < e; ++i) r *= b;
   return r;
+}
+
+// staging of amr_set_state_prim: at most 16 Mi doubles (128 MiB, or one patch
+// if larger) and 64 Ki patches per batch
+constexpr long long kPrimStageDoubles = 16LL << 20;
+constexpr long long kPrimStagePatches = 65536;
+
+// one contiguous copy: device offset, host offset, doubles
+struct CopyRun {
+  long long dev, host, count;
+};
+
+// the whole patch arrays of `pids`, concatenated on the host in pid order,
+// as copies merged where consecutive pids sit next to each other in their
+// level's pool; throws on an inactive pid before anything is copied
+std::vector<CopyRun> copy_runs(const amr_hierarchy* h, const int* pids, int npatch) {
+  std::vector<CopyRun> runs;
+  long long pos = 0;
+  for (int i = 0; i < npatch; ++i) {
+    int64_t off;
+    if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
+    const long long cnt = h->dm.lv[h->forest.level[pids[i]]].stride;
+    if (!runs.empty() && runs.back().dev + runs.back().count == off)
+      runs.back().count += cnt;
+    else
+      runs.push_back({off, pos, cnt});
+    pos += cnt;
+  }
+  return runs;
 }
 
 void validate_config(const amr_config& c) {
@@ -890,15 +928,10 @@ amr_status amr_set_state(amr_hierarchy* h, int buf, const double* host, const in
   if (!h || !buf_ok(buf) || (npatch > 0 && (!host || !pids))) return AMR_E_ARG;
   h->lam_valid = false;
   return guarded(h, [&]() -> amr_status {
-    long long pos = 0;
-    for (int i = 0; i < npatch; ++i) {
-      int64_t off;
-      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
-      const long long cnt = h->dm.lv[h->forest.level[pids[i]]].stride;
-      HIP_OK(hipMemcpyAsync(h->U[buf] + off, host + pos, cnt * sizeof(double),
+    const std::vector<CopyRun> runs = copy_runs(h, pids, npatch);
+    for (const CopyRun& r : runs)
+      HIP_OK(hipMemcpyAsync(h->U[buf] + r.dev, host + r.host, r.count * sizeof(double),
                             hipMemcpyHostToDevice, h->stream));
-      pos += cnt;
-    }
     h->sync();
     return AMR_OK;
   });
@@ -909,15 +942,10 @@ amr_status amr_get_state(const amr_hierarchy* hc, int buf, double* host, const i
   amr_hierarchy* h = const_cast<amr_hierarchy*>(hc);
   if (!h || !buf_ok(buf) || (npatch > 0 && (!host || !pids))) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
-    long long pos = 0;
-    for (int i = 0; i < npatch; ++i) {
-      int64_t off;
-      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
-      const long long cnt = h->dm.lv[h->forest.level[pids[i]]].stride;
-      HIP_OK(hipMemcpyAsync(host + pos, h->U[buf] + off, cnt * sizeof(double),
+    const std::vector<CopyRun> runs = copy_runs(h, pids, npatch);
+    for (const CopyRun& r : runs)
+      HIP_OK(hipMemcpyAsync(host + r.host, h->U[buf] + r.dev, r.count * sizeof(double),
                             hipMemcpyDeviceToHost, h->stream));
-      pos += cnt;
-    }
     h->sync();
     return AMR_OK;
   });
@@ -928,42 +956,51 @@ amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* prim, con
   if (!h || !buf_ok(buf) || (npatch > 0 && (!prim || !pids))) return AMR_E_ARG;
   h->lam_valid = false;
   return guarded(h, [&]() -> amr_status {
+    if (npatch == 0) return AMR_OK;
     const int d = h->cfg.dim, nv = h->nvar;
-    const double gm1 = h->cfg.gamma - 1.0;
-    long long pos = 0;
+    // source offset of every patch, all pids checked before anything is written
+    std::vector<long long> pos(npatch + 1, 0);
+    long long largest = 0;
     for (int i = 0; i < npatch; ++i) {
       int64_t off;
       if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
-      const amr::LevelC& L = h->dm.lv[h->forest.level[pids[i]]];
-      const long long cells = ipow(L.n, d);
-      const long long box = ipow(L.full, d);
-      std::vector<double> patch(L.stride);
-      HIP_OK(hipMemcpyAsync(patch.data(), h->U[buf] + off, L.stride * sizeof(double),
-                            hipMemcpyDeviceToHost, h->stream));
-      h->sync();
-      for (long long c = 0; c < cells; ++c) {
-        const int x = (int)(c % L.n);
-        const int y = d >= 2 ? (int)((c / L.n) % L.n) : 0;
-        const int z = d >= 3 ? (int)(c / ((long long)L.n * L.n)) : 0;
-        long long b = x + amr::kNG;
-        if (d >= 2) b += (long long)(y + amr::kNG) * L.full;
-        if (d >= 3) b += (long long)(z + amr::kNG) * L.full * L.full;
-        const double rho = prim[pos + c];
-        double uu = 0.0;
-        for (int j = 0; j < d; ++j) {
-          const double u = prim[pos + (1 + j) * cells + c];
-          uu = (j == 0) ? u * u : uu + u * u;
-          patch[(1 + j) * box + b] = rho * u;
-        }
-        const double p = prim[pos + (d + 1) * cells + c];
-        patch[b] = rho;
-        patch[(nv - 1) * box + b] = p / gm1 + 0.5 * rho * uu;
-      }
-      HIP_OK(hipMemcpyAsync(h->U[buf] + off, patch.data(), L.stride * sizeof(double),
-                            hipMemcpyHostToDevice, h->stream));
-      h->sync();
-      pos += (long long)nv * cells;
+      const long long cnt = (long long)nv * ipow(h->dm.lv[h->forest.level[pids[i]]].n, d);
+      pos[i + 1] = pos[i] + cnt;
+      largest = std::max(largest, cnt);
     }
+    // batches of whole patches through one device staging buffer
+    const long long cap = std::max(largest, std::min<long long>(pos[npatch], kPrimStageDoubles));
+    const int max_batch = (int)std::min<long long>(npatch, kPrimStagePatches);
+    const size_t bytes = (size_t)cap * sizeof(double) + (size_t)max_batch * (sizeof(long long) + sizeof(int));
+    char* stage = (char*)h->dev_alloc(bytes);
+    double* d_prim = (double*)stage;
+    long long* d_src = (long long*)(stage + (size_t)cap * sizeof(double));
+    int* d_pids = (int*)(d_src + max_batch);
+    std::vector<long long> src;
+    try {
+      for (int i = 0; i < npatch;) {
+        int j = i;
+        while (j < npatch && j - i < max_batch && pos[j + 1] - pos[i] <= cap) ++j;
+        src.resize(j - i);
+        for (int k = i; k < j; ++k) src[k - i] = pos[k] - pos[i];
+        HIP_OK(hipMemcpyAsync(d_prim, prim + pos[i], (pos[j] - pos[i]) * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+        HIP_OK(hipMemcpyAsync(d_src, src.data(), src.size() * sizeof(long long),
+                              hipMemcpyHostToDevice, h->stream));
+        HIP_OK(hipMemcpyAsync(d_pids, pids + i, (j - i) * sizeof(int), hipMemcpyHostToDevice,
+                              h->stream));
+        amr::StateIO::set_prim(h->dm, h->U[buf], d_prim, d_src, d_pids, j - i,
+                               h->cfg.gamma - 1.0, h->stream);
+        h->check_launch();
+        h->sync();  // the staging buffer and src are reused by the next batch
+        i = j;
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(h->stream);
+      h->dev_free(stage);
+      throw;
+    }
+    h->dev_free(stage);
     return AMR_OK;
   });
 }

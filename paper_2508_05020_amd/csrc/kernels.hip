@@ -752,7 +752,12 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
         k_fill_cf<2, 128><<<count, 128, 0, s>>>(m, U, list, count, err);
       break;
     }
-    default: k_fill_cf<3, 256><<<count, 256, 0, s>>>(m, U, list, count, err); break;
+    default:
+      // a region of an 8^3 patch is 64, 128 or 256 cells and one of a 16^3
+      // patch 64 to 1024: one wave per region keeps every lane busy; the
+      // waves of a 256-thread block beyond a corner's 64 cells would idle
+      k_fill_cf<3, 64><<<count, 64, 0, s>>>(m, U, list, count, err);
+      break;
   }
 }
 
