@@ -118,6 +118,155 @@ __global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m, double* __restrict__ 
   }
 }
 
+// The same regions by coarse cell (2D and 3D).  A region's start and extent
+// are even in every dimension, so its fine cells come in aligned blocks of
+// 2^D, and both cells of an aligned pair have the same coarse cell also
+// after the boundary mapping (a periodic wrap of an even cell count keeps
+// pairs together; the clamp sends a whole out-of-domain pair to one edge
+// cell).  One thread computes the coarse stencil, the MC slopes and the
+// positivity test once and forms each of the 2^D fine values as
+// prolong_cell does, in the same operation order, so the values are bitwise
+// those of the per-fine-cell fill.  A block takes G consecutive regions and
+// spreads all their coarse cells over its lanes: a 3D region covers as few
+// as 8 coarse cells (a corner).
+template <int D, int NT, int G>
+__global__ __launch_bounds__(NT) void k_fill_cf_coarse(DevMesh m, double* __restrict__ U,
+                                                       const int* __restrict__ list, int count,
+                                                       int* __restrict__ err) {
+  constexpr int NV = D + 2, NS = 2 * D + 1, NF = 1 << D;
+  __shared__ int s_pid[G], s_code[G], s_pre[G + 1];
+  const int first = blockIdx.x * G;
+  if (first >= count) return;
+  if (threadIdx.x < G) {
+    const int i = first + (int)threadIdx.x;
+    int pid = -1, code = 0, cnt = 0;
+    if (i < count) {
+      pid = list[2 * i];
+      code = list[2 * i + 1];
+      const int n = m.lv[m.level[pid]].n;
+      cnt = 1;
+      for (int j = 0; j < D; ++j) {
+        const int r = (j == 0 ? code : (j == 1 ? code / 3 : code / 9)) % 3 - 1;
+        cnt *= (r == 0 ? n : NG) / 2;
+      }
+    }
+    s_pid[threadIdx.x] = pid;
+    s_code[threadIdx.x] = code;
+    s_pre[threadIdx.x + 1] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pre[0] = 0;
+    for (int i = 0; i < G; ++i) s_pre[i + 1] += s_pre[i];
+  }
+  __syncthreads();
+  const int total = s_pre[G];
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    int it = 0;
+    while (idx >= s_pre[it + 1]) ++it;
+    const int pid = s_pid[it], code = s_code[it];
+    const int local = idx - s_pre[it];
+    const int l = m.level[pid];
+    const LevelC& L = m.lv[l];
+    const int n = L.n, full = L.full;
+    const long long vs = var_stride<D>(full);
+    double* P = U + patch_base(m, pid, l);
+    int start[3] = {0, 0, 0}, half[3] = {1, 1, 1};
+    for (int j = 0; j < D; ++j) {
+      const int r = (j == 0 ? code : (j == 1 ? code / 3 : code / 9)) % 3 - 1;
+      start[j] = r < 0 ? -NG : (r == 0 ? 0 : n);
+      half[j] = (r == 0 ? n : NG) / 2;
+    }
+    const int k[3] = {local % half[0], (local / half[0]) % half[1], local / (half[0] * half[1])};
+    int c0[3] = {0, 0, 0}, gc[3] = {0, 0, 0};
+    double sg[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int j = 0; j < D; ++j) {
+      const int pcj = m.coord[3 * pid + j];
+      c0[j] = start[j] + 2 * k[j];
+      const int g0 = bc_map(pcj * n + c0[j], L.cells, m.periodic[j]);
+      const int g1 = bc_map(pcj * n + c0[j] + 1, L.cells, m.periodic[j]);
+      gc[j] = g0 >> 1;
+      sg[j][0] = (g0 & 1) ? 1.0 : -1.0;
+      sg[j][1] = (g1 & 1) ? 1.0 : -1.0;
+    }
+    const int lc = l > 0 ? l - 1 : 0;
+    const LevelC& C = m.lv[lc];
+    const long long vsc = var_stride<D>(C.full);
+    int pids[NS];
+    long long offs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      int gs[3] = {gc[0], gc[1], gc[2]};
+      if (s > 0) {
+        const int j = (s - 1) >> 1;
+        gs[j] = bc_map(gc[j] + (((s - 1) & 1) ? -1 : 1), C.cells, m.periodic[j]);
+      }
+      int q[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+      for (int j = 0; j < D; ++j) {
+        q[j] = gs[j] / C.n;
+        c[j] = gs[j] - q[j] * C.n;
+      }
+      pids[s] = l > 0 ? map_at<D>(m, lc, q) : -1;
+      offs[s] = box_off<D>(C.full, c[0] + NG, c[1] + NG, c[2] + NG);
+    }
+    bool found = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) found &= pids[s] >= 0;
+    if (!found) {
+      err[0] = 1;
+      for (int f = 0; f < NF; ++f) {
+        const long long off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
+                                         c0[2] + ((f >> 2) & 1) + NG);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P[v * vs + off] = __builtin_nan("");
+      }
+      continue;
+    }
+    double val[NS][NV];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double* Q = U + patch_base(m, pids[s], lc) + offs[s];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) val[s][v] = Q[v * vsc];
+    }
+    const double* phi = val[0];
+    double sl[D][NV];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double a = val[1 + 2 * j][v] - phi[v];
+        const double b = phi[v] - val[2 + 2 * j][v];
+        const bool same = (a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0);
+        const double mag = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
+        sl[j][v] = same ? copysign(mag, a) : 0.0;
+      }
+    }
+    bool bad = false;
+    for (int c = 0; c < NF; ++c) {
+      double ch[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double x = phi[v];
+        for (int j = 0; j < D; ++j) x = x + (((c >> j) & 1) ? 0.25 : -0.25) * sl[j][v];
+        ch[v] = x;
+      }
+      const double p = pressure_exact<D>(ch, m.gm1);
+      if (!(ch[0] > 0.0 && p > 0.0)) bad = true;
+    }
+    for (int f = 0; f < NF; ++f) {
+      const long long off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
+                                       c0[2] + ((f >> 2) & 1) + NG);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double x = phi[v];
+        for (int j = 0; j < D; ++j) x = x + (sg[j][(f >> j) & 1] * 0.25) * (bad ? 0.0 : sl[j][v]);
+        P[v * vs + off] = x;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // coarse/fine flux correction: list of (pid, face mask); faces are processed
 // in the order x-, x+, y-, y+, z-, z+ so that corner cells see a fixed order
@@ -742,8 +891,10 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
   switch (m.dim) {
     case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
     case 2: {
-      // one cell per thread: a side region is 4 n cells (64 at n = 16, 128 at
-      // n = 32); level 0 has no prolonged ghosts
+      // one fine cell per thread: a side region is 4 n cells (64 at n = 16,
+      // 128 at n = 32); level 0 has no prolonged ghosts.  (The coarse-cell
+      // form below is slower here: a 2D mesh has a few thousand regions, and
+      // packing them leaves fewer blocks than compute units.)
       int nmax = 0;
       for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
       if (nmax <= 16)
@@ -753,10 +904,9 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
       break;
     }
     default:
-      // a region of an 8^3 patch is 64, 128 or 256 cells and one of a 16^3
-      // patch 64 to 1024: one wave per region keeps every lane busy; the
-      // waves of a 256-thread block beyond a corner's 64 cells would idle
-      k_fill_cf<3, 64><<<count, 64, 0, s>>>(m, U, list, count, err);
+      // one thread per coarse cell, 8 regions per wave: a region of an 8^3
+      // patch covers 8, 16 or 32 coarse cells and one of a 16^3 patch 8 to 128
+      k_fill_cf_coarse<3, 64, 8><<<(count + 7) / 8, 64, 0, s>>>(m, U, list, count, err);
       break;
   }
 }
