@@ -135,6 +135,11 @@ struct amr_hierarchy {
     if (has_alloc) {
       p = alloc.alloc(bytes, alloc.ctx);
       if (!p) throw HipError("device allocator returned NULL");
+      // kernels load aligned pairs of doubles as 16-byte vectors
+      if (reinterpret_cast<uintptr_t>(p) & 255) {
+        alloc.free(p, alloc.ctx);
+        throw ArgError("device allocator returned memory not aligned to 256 B");
+      }
     } else {
       HIP_OK(hipMalloc(&p, bytes));
     }

@@ -449,16 +449,20 @@ __device__ __forceinline__ void restrict_cell(const DevMesh& m, double* __restri
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const double* S = Pc + v * vsf;
-    auto at = [&](int x, int y, int z) {
-      return S[box_off<D>(F.full, 2 * a + x + NG, 2 * b + y + NG, 2 * c + z + NG)];
+    // sum of the x-pair (2a, 2a + 1) of fine row (y, z), read as one 16-byte
+    // load: every offset here is even (even patch edges, ghost width 4, pools
+    // of whole patches) and the state buffer is 256-byte aligned
+    auto xsum = [&](int y, int z) {
+      const double2 t = *reinterpret_cast<const double2*>(
+          S + box_off<D>(F.full, 2 * a + NG, 2 * b + y + NG, 2 * c + z + NG));
+      return t.x + t.y;
     };
     double r;
-    if constexpr (D == 1) r = (at(0, 0, 0) + at(1, 0, 0)) * 0.5;
+    if constexpr (D == 1) r = xsum(0, 0) * 0.5;
     else if constexpr (D == 2)
-      r = ((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) * 0.25;
+      r = (xsum(0, 0) + xsum(1, 0)) * 0.25;
     else
-      r = (((at(0, 0, 0) + at(1, 0, 0)) + (at(0, 1, 0) + at(1, 1, 0))) +
-           ((at(0, 0, 1) + at(1, 0, 1)) + (at(0, 1, 1) + at(1, 1, 1)))) * 0.125;
+      r = ((xsum(0, 0) + xsum(1, 0)) + (xsum(0, 1) + xsum(1, 1))) * 0.125;
     Pp[v * vsc + dst] = r;
   }
 }
