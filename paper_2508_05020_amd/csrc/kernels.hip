@@ -895,16 +895,19 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
   switch (m.dim) {
     case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
     case 2: {
-      // one fine cell per thread: a side region is 4 n cells (64 at n = 16,
-      // 128 at n = 32); level 0 has no prolonged ghosts.  (The coarse-cell
-      // form below is slower here: a 2D mesh has a few thousand regions, and
-      // packing them leaves fewer blocks than compute units.)
+      // refined patches of edge 16 or less: one fine cell per thread (a side
+      // region is 4 n = 64 cells); wider ones: by coarse cell, two regions
+      // per wave (a side region of a 32^2 patch is 64 coarse cells).  Level 0
+      // has no prolonged ghosts.  Per launch: C2 (16^2) 7.2 us per fine
+      // cell, 10.1 / 8.5 / 11.1 us by coarse cell with 1 / 2 / 8 regions per
+      // block; C4 (32^2) 30.3 us per fine cell (128 threads), 34.1 / 25.4 us
+      // by coarse cell with 1 / 2 regions per block.
       int nmax = 0;
       for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
       if (nmax <= 16)
         k_fill_cf<2, 64><<<count, 64, 0, s>>>(m, U, list, count, err);
       else
-        k_fill_cf<2, 128><<<count, 128, 0, s>>>(m, U, list, count, err);
+        k_fill_cf_coarse<2, 64, 2><<<(count + 1) / 2, 64, 0, s>>>(m, U, list, count, err);
       break;
     }
     default:

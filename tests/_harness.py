@@ -28,6 +28,13 @@ def case_config(name: str):
         cfg = W.AMRConfig(name="p2w", dim=2, base_cells=64, patch_cells=[16, 16, 16],
                           periodic=[False, True], ic="quadrants_blobs", max_patches=2048)
         return cfg, W.quadrants_blobs(2002), None
+    if name == "2d-32":
+        # refined levels of 32^2 patches (the wide coarse/fine fill), one
+        # transmissive direction
+        cfg = W.AMRConfig(name="p2l", dim=2, base_cells=64, patch_cells=[16, 32, 32],
+                          periodic=[True, False], ic="quadrants_blobs", max_patches=1024)
+        picks = [[(0, (1, 1))], [(1, (1, 1))]]
+        return cfg, W.quadrants_blobs(2003), picks
     if name == "implosion":
         # the paper's implosion problem (Eq. (13)) on (-0.3, 0.3)^2
         cfg = W.AMRConfig(name="pimp", dim=2, base_cells=32, patch_cells=[16, 16, 16],

@@ -18,7 +18,7 @@ from tests import _harness as H
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["1d", "2d", "2d-wall", "implosion", "3d", "3d-uneven"]
+CASES = ["1d", "2d", "2d-wall", "2d-32", "implosion", "3d", "3d-uneven"]
 
 
 @pytest.fixture(scope="module")
