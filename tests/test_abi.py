@@ -103,8 +103,10 @@ def test_forest_replay_capacity_error():
     assert e.value.status == -2
 
 
-@pytest.mark.parametrize("dim,base,nrefine", [(2, 1024, 300), (3, 256, 80)])
-def test_forest_replay_order_large(dim, base, nrefine):
+@pytest.mark.parametrize("dim,base,nrefine,small_cap", [(1, 65536, 300, 6000),
+                                                      (2, 1024, 300, 9000),
+                                                      (3, 256, 80, 20000)])
+def test_forest_replay_order_large(dim, base, nrefine, small_cap):
     """Active patches come out in (level, z, y, x) order from both host
     paths: the level-map scan (capacity large against the maps) and the
     packed-key radix sort (capacity small against the maps, >= 4096 keys)."""
@@ -117,7 +119,7 @@ def test_forest_replay_order_large(dim, base, nrefine):
               ([(1, tuple(2 * x + rnd.randrange(2) for x in c)) for c in coords[:nsub]], []),
               ([], [(0, c) for c in coords[c0:c0 + nrefine // 5]])]
     outs = []
-    for mp in ((9000 if dim == 2 else 20000), 400000):
+    for mp in (small_cap, 400000):
         cfg = W.AMRConfig(name="m", dim=dim, base_cells=base, patch_cells=[16, 16, 16],
                           periodic=[True] * dim, max_patches=mp)
         outs.append([(r[0], r[1], r[3]) for r in A.forest_replay(cfg, rounds)])
