@@ -2,11 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or run
 anything in this package: only the tests, the smoke check and the CPU-baseline
-leg of the benchmark do.  The oracle shares no code with the HIP library; the
-only module both sides use is ``paper_2508_05020_amd.workloads`` (run
-configurations and seeded primitive initial data, no method arithmetic).
+leg of the benchmark do.  The oracle shares no code with the HIP library and
+imports nothing from the product package: it reads the plain numbers of a run
+description (``geometry.Grid``) and takes initial data as a callable that
+returns primitive fields at given points (the seeded generators live in their
+own module, which holds none of the method's arithmetic).
 
 Modules
+  geometry  -- level geometry: cell counts, widths h_l and cell centres.
   euler     -- per-patch right-hand side: primitives (Eq. 4-7), WENO5-JS point
                interpolation, Rusanov flux (Eq. 10-12), staggered divergence
                (Eq. 9 in conservative flux form).

@@ -35,12 +35,12 @@ def _shift(a: np.ndarray, axis: int, s: int, ng: int) -> np.ndarray:
 def velocity_gradient(o, buf: int) -> Dict:
     """Per leaf key, an array [d*d + 1, n, ...] (interior cells, array axes
     z, y, x): G[i][j] at component i*d + j, then S."""
-    d = o.cfg.dim
-    ng = o.cfg.ghost
+    d = o.grid.dim
+    ng = o.grid.ghost
     out = {}
     for key in o.forest.leaves():
         U = o.U[buf][key]
-        h = o.cfg.h(key[0])
+        h = o.grid.h(key[0])
         rho = U[0]
         vel = [U[1 + i] / rho for i in range(d)]
         comps = []

@@ -29,6 +29,8 @@ from __future__ import annotations
 import itertools
 from typing import Dict, List, Optional, Tuple
 
+from .geometry import Grid
+
 Key = Tuple[int, Tuple[int, ...]]
 
 
@@ -43,7 +45,10 @@ def order_key(key: Key):
 
 class Forest:
     def __init__(self, cfg, coarsen_rule: str = "text"):
-        self.cfg = cfg
+        # the forest's own copy of the level geometry (a run description is
+        # converted; an oracle Grid is used as it is)
+        self.cfg = cfg if isinstance(cfg, Grid) else Grid(cfg)
+        cfg = self.cfg
         self.d = cfg.dim
         self.coarsen_rule = coarsen_rule
         self.parent: Dict[Key, Optional[Key]] = {}

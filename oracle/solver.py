@@ -41,8 +41,8 @@ from typing import Dict, List
 
 import numpy as np
 
-from paper_2508_05020_amd import workloads
 from . import euler
+from .geometry import Grid
 from .mesh import Forest, MeshError, order_key
 
 
@@ -53,13 +53,15 @@ def _idx(canvas_arrays, g):
 
 class OracleAMR:
     def __init__(self, cfg, coarsen_rule: str = "text", scheme: str = "weno"):
-        cfg.validate()
+        # ``cfg`` is the run description; the oracle copies its numbers into
+        # its own Grid and computes every length and sample point from those
         self.cfg = cfg
-        self.d = cfg.dim
-        self.ng = cfg.ghost
-        self.nvar = cfg.nvar
+        self.grid = Grid(cfg)
+        self.d = self.grid.dim
+        self.ng = self.grid.ghost
+        self.nvar = self.grid.nvar
         self.scheme = scheme
-        self.forest = Forest(cfg, coarsen_rule)
+        self.forest = Forest(self.grid, coarsen_rule)
         self.U: List[Dict] = [{}, {}, {}]
         for key in self.forest.keys():
             self._alloc(key)
@@ -68,7 +70,7 @@ class OracleAMR:
 
     # ------------------------------------------------------------------ data
     def _alloc(self, key):
-        n = self.cfg.patch_cells[key[0]]
+        n = self.grid.patch_cells[key[0]]
         shape = (self.nvar,) + (n + 2 * self.ng,) * self.d
         for b in range(3):
             self.U[b][key] = np.zeros(shape)
@@ -79,16 +81,16 @@ class OracleAMR:
 
     def set_initial(self, key, gen, buf: int = 0):
         level, coord = key
-        pts = workloads.patch_points(self.cfg, level, coord)
+        pts = self.grid.points(level, coord)
         rho, u, p = gen(pts)
         self.interior(self.U[buf][key])[...] = euler.conserved_from_primitive(
-            rho, u, p, self.cfg.gamma)
+            rho, u, p, self.grid.gamma)
 
     def canvas(self, buf: int, level: int):
         """Level-wide array holding the interiors of all active patches (NaN
         elsewhere) and the presence map of level patches."""
-        N = self.cfg.cells(level)
-        n = self.cfg.patch_cells[level]
+        N = self.grid.cells(level)
+        n = self.grid.patch_cells[level]
         arr = np.full((self.nvar,) + (N,) * self.d, np.nan)
         present = np.zeros((self.forest.npd(level),) * self.d, dtype=bool)
         for key, a in self.U[buf].items():
@@ -101,17 +103,17 @@ class OracleAMR:
         return arr, present
 
     def bc_map(self, level: int, g):
-        N = self.cfg.cells(level)
+        N = self.grid.cells(level)
         out = []
         for j in range(self.d):
-            if self.cfg.periodic[j]:
+            if self.grid.periodic[j]:
                 out.append(np.mod(g[j], N))
             else:
                 out.append(np.clip(g[j], 0, N - 1))
         return out
 
     def _present_at(self, level, present, g):
-        n = self.cfg.patch_cells[level]
+        n = self.grid.patch_cells[level]
         return present[tuple(reversed([gj // n for gj in g]))]
 
     # ---------------------------------------------------------- prolongation
@@ -146,7 +148,7 @@ class OracleAMR:
             ch = phi
             for j in range(d):
                 ch = ch + (signs[j] * 0.25) * slopes[j]
-            rho, _, p, _ = euler.primitives(ch, d, self.cfg.gamma)
+            rho, _, p, _ = euler.primitives(ch, d, self.grid.gamma)
             bad |= ~((rho > 0.0) & (p > 0.0))
         val = phi
         for j in range(d):
@@ -172,7 +174,7 @@ class OracleAMR:
 
         for key in keys:
             level, coord = key
-            n = self.cfg.patch_cells[level]
+            n = self.grid.patch_cells[level]
             loc = self._local_grid(n)
             ghost = np.zeros(loc[0].shape, dtype=bool)
             for j in range(self.d):
@@ -196,7 +198,7 @@ class OracleAMR:
     def face_fluxes(self, buf: int):
         """Face fluxes of every leaf, with coarse faces on coarse/fine
         interfaces replaced by the mean of the fine face fluxes."""
-        cfg, d = self.cfg, self.d
+        cfg, d = self.grid, self.d
         leaves = self.forest.leaves()
         faces = {k: euler.patch_faces(self.U[buf][k], d, cfg.gamma, cfg.weno_eps,
                                       self.ng, self.scheme) for k in leaves}
@@ -268,7 +270,7 @@ class OracleAMR:
     def rhs(self, buf: int) -> Dict:
         """L(U) on every leaf (ghosts of ``buf`` must be filled)."""
         faces = self.face_fluxes(buf)
-        return {k: euler.divergence(f, self.d, self.cfg.h(k[0])) for k, f in faces.items()}
+        return {k: euler.divergence(f, self.d, self.grid.h(k[0])) for k, f in faces.items()}
 
     # ---------------------------------------------------------- restriction
     def restrict(self, buf: int):
@@ -277,10 +279,10 @@ class OracleAMR:
             for key in self.forest.keys():
                 if key[0] != level or self.forest.is_leaf(key):
                     continue
-                n = self.cfg.patch_cells[level]
+                n = self.grid.patch_cells[level]
                 pin = self.interior(self.U[buf][key])
                 for ck in self.forest.children[key]:
-                    nf = self.cfg.patch_cells[level + 1]
+                    nf = self.grid.patch_cells[level + 1]
                     c = self.interior(self.U[buf][ck])
                     h = nf // 2
                     o = [ck[1][j] * h - key[1][j] * n for j in range(d)]
@@ -302,11 +304,11 @@ class OracleAMR:
         lam = 0.0
         for k in self.forest.leaves():
             lam = max(lam, euler.max_wave_rate(self.interior(self.U[buf][k]), self.d,
-                                               self.cfg.h(k[0]), self.cfg.gamma))
+                                               self.grid.h(k[0]), self.grid.gamma))
         return lam
 
     def compute_dt(self, buf: int = 0) -> float:
-        return self.cfg.cfl / self.max_rate(buf)
+        return self.grid.cfl / self.max_rate(buf)
 
     def stage(self, k: int, dt: float):
         src = {1: 0, 2: 1, 3: 2}[k]
@@ -351,7 +353,7 @@ class OracleAMR:
     def tag(self, buf: int = 0):
         """Tag flag of every patch of ``tag_keys()`` and per-cell dilated tags
         (ghosts of those patches filled)."""
-        cfg, d, ng = self.cfg, self.d, self.ng
+        cfg, d, ng = self.grid, self.d, self.ng
         b = cfg.tag_buffer
         has, cells = {}, {}
         for key in self.tag_keys():
@@ -383,7 +385,7 @@ class OracleAMR:
         whose own restricted data are untagged too (without the last
         condition a feature that the tagger sees on a coarse level but not
         on the finer one would be refined and coarsened in turn)."""
-        L = self.cfg.max_levels
+        L = self.grid.max_levels
         refine = [k for k in self.forest.leaves() if k[0] < L - 1 and has[k]]
         coarsen = [k for k in self.coarsening_candidates()
                    if not has[k] and not any(has[c] for c in self.forest.children[k])]
@@ -405,7 +407,7 @@ class OracleAMR:
                     self.set_initial(k, gen)
                 continue
             coarse = self.canvas(0, level - 1)
-            n = self.cfg.patch_cells[level]
+            n = self.grid.patch_cells[level]
             for k in new:
                 loc = self._local_grid(n)
                 inner = np.ones(loc[0].shape, dtype=bool)
@@ -431,7 +433,7 @@ class OracleAMR:
         for k in self.forest.keys():
             self.set_initial(k, gen)
         history = []
-        for _ in range(self.cfg.max_levels - 1):
+        for _ in range(self.grid.max_levels - 1):
             self.fill_ghosts(0, self.tag_keys())
             has, _ = self.tag(0)
             refine, _ = self.requests(has)
@@ -444,8 +446,8 @@ class OracleAMR:
     def advance(self, nsteps: int, regrid: bool = True):
         for _ in range(nsteps):
             self.step()
-            if regrid and self.cfg.regrid_interval > 0 \
-                    and self.nsteps % self.cfg.regrid_interval == 0:
+            if regrid and self.grid.regrid_interval > 0 \
+                    and self.nsteps % self.grid.regrid_interval == 0:
                 self.adapt()
 
     # ----------------------------------------------------------- diagnostics
@@ -455,10 +457,10 @@ class OracleAMR:
         for v in range(self.nvar):
             vals = []
             for k in self.forest.leaves():
-                hd = self.cfg.h(k[0]) ** self.d
+                hd = self.grid.h(k[0]) ** self.d
                 vals.extend((self.interior(self.U[buf][k])[v] * hd).ravel().tolist())
             out.append(math.fsum(vals))
         return out
 
     def leaf_cells(self) -> int:
-        return sum(self.cfg.patch_cells[k[0]] ** self.d for k in self.forest.leaves())
+        return sum(self.grid.patch_cells[k[0]] ** self.d for k in self.forest.leaves())
