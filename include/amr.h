@@ -137,6 +137,22 @@ amr_status amr_get_state(const amr_hierarchy* h, int buf, double* host, const in
 amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* host_prim,
                               const int* pids, int npatch);
 
+/* amr_set_state_prim for callers that cannot allocate device memory (code
+ * under HIP graph capture excepted: the call copies from host memory and
+ * waits): the same conversion and result, staged through a fixed per-GPU
+ * scratch array of AMR_NOALLOC_SCRATCH_BYTES that the library holds from
+ * its first hierarchy on that GPU until the process ends, instead of a
+ * buffer from the allocator; no hipMalloc, hipFree or allocator call.
+ * One call takes at most AMR_NOALLOC_SCRATCH_BYTES of primitives and patch
+ * indices (8 bytes per interior value, rounded up to 256 bytes, plus 12
+ * bytes per patch); a larger call is AMR_E_ARG before anything is copied
+ * (split the patches over several calls).  Sync.  Every hierarchy on one GPU
+ * shares that GPU's scratch, so calls that overlap in time on one GPU (from
+ * several host threads) race; calls from one thread never overlap. */
+enum { AMR_NOALLOC_SCRATCH_BYTES = 32 << 20 };
+amr_status amr_set_state_prim_noalloc(amr_hierarchy* h, int buf, const double* host_prim,
+                                      const int* pids, int npatch);
+
 /* Ghost fill of every active patch of buffer `buf` (async): same-level
  * source where an active same-level patch covers the (wrapped or clamped)
  * ghost position, otherwise conservative MC-limited linear prolongation

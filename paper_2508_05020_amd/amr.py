@@ -30,6 +30,7 @@ MAX_LEVELS = 8
 EXEC_PER_PATCH, EXEC_BATCHED = 0, 1
 COARSEN_TEXT, COARSEN_LITERAL = 0, 1
 SCHEME_WENO, SCHEME_CENTRAL = 0, 1
+NOALLOC_SCRATCH_BYTES = 32 << 20   # AMR_NOALLOC_SCRATCH_BYTES
 
 STATUS = {0: "AMR_OK", -1: "AMR_E_ARG", -2: "AMR_E_CAPACITY", -3: "AMR_E_HIP",
           -4: "AMR_E_MESH", -5: "AMR_E_NONPHYSICAL", -6: "AMR_E_STATE"}
@@ -85,6 +86,7 @@ _sigs = {
     "amr_set_state": [_H, C.c_int, C.c_void_p, _P(C.c_int), C.c_int],
     "amr_get_state": [_H, C.c_int, C.c_void_p, _P(C.c_int), C.c_int],
     "amr_set_state_prim": [_H, C.c_int, C.c_void_p, _P(C.c_int), C.c_int],
+    "amr_set_state_prim_noalloc": [_H, C.c_int, C.c_void_p, _P(C.c_int), C.c_int],
     "amr_fill_ghosts": [_H, C.c_int],
     "amr_rhs": [_H, C.c_int, C.c_void_p],
     "amr_compute_dt": [_H, C.c_int, C.c_void_p],
@@ -319,6 +321,15 @@ class Hierarchy:
                                                     for p in pids])) if pids else np.zeros(1)
         self._ok(_lib.amr_set_state_prim(self.h, buf, data.ctypes.data_as(C.c_void_p),
                                          self._pids(pids), len(pids)))
+
+    def set_state_prim_noalloc(self, buf: int, prims: Dict[int, np.ndarray]):
+        """set_state_prim through the library's fixed per-GPU scratch (no
+        device allocation; at most NOALLOC_SCRATCH_BYTES per call)."""
+        pids = list(prims)
+        data = np.ascontiguousarray(np.concatenate([np.asarray(prims[p], np.float64).ravel()
+                                                    for p in pids])) if pids else np.zeros(1)
+        self._ok(_lib.amr_set_state_prim_noalloc(self.h, buf, data.ctypes.data_as(C.c_void_p),
+                                                 self._pids(pids), len(pids)))
 
     # -- hot path ------------------------------------------------------------
     def fill_ghosts(self, buf: int):

@@ -46,6 +46,9 @@ struct amr_hierarchy {
   amr::Forest forest;
   amr::DevMesh dm{};
   hipStream_t stream = nullptr;
+  // device address of the staging array of amr_set_state_prim_noalloc on this
+  // hierarchy's device (resolved at creation)
+  void* noalloc_scratch = nullptr;
   amr_allocator alloc{};
   bool has_alloc = false;
   std::string err;
@@ -774,6 +777,7 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     validate_config(*cfg);
     h->cfg = *cfg;
     h->stream = (hipStream_t)hip_stream;
+    HIP_OK(amr::StateIO::noalloc_scratch(&h->noalloc_scratch));
     if (alloc && alloc->alloc && alloc->free) {
       h->alloc = *alloc;
       h->has_alloc = true;
@@ -1006,6 +1010,53 @@ amr_status amr_set_state_prim(amr_hierarchy* h, int buf, const double* prim, con
       throw;
     }
     h->dev_free(stage);
+    return AMR_OK;
+  });
+}
+
+static_assert(AMR_NOALLOC_SCRATCH_BYTES == amr::StateIO::kScratchBytes,
+              "header and library disagree on the no-allocation scratch size");
+
+amr_status amr_set_state_prim_noalloc(amr_hierarchy* h, int buf, const double* prim,
+                                      const int* pids, int npatch) {
+  if (!h || !buf_ok(buf) || npatch < 0 || (npatch > 0 && (!prim || !pids))) return AMR_E_ARG;
+  return guarded(h, [&]() -> amr_status {
+    if (npatch == 0) return AMR_OK;
+    const int d = h->cfg.dim, nv = h->nvar;
+    // scratch layout: primitive values, then (256-byte aligned) the source
+    // offset of every patch, then the pids; everything is checked before
+    // anything is copied
+    std::vector<long long> src(npatch);
+    long long total = 0;
+    for (int i = 0; i < npatch; ++i) {
+      int64_t off;
+      if (amr_patch_offset(h, pids[i], &off) != AMR_OK) throw ArgError("inactive pid");
+      src[i] = total;
+      total += (long long)nv * ipow(h->dm.lv[h->forest.level[pids[i]]].n, d);
+    }
+    const size_t prim_bytes = ((size_t)total * sizeof(double) + 255) & ~(size_t)255;
+    const size_t need = prim_bytes + (size_t)npatch * (sizeof(long long) + sizeof(int));
+    if (need > amr::StateIO::kScratchBytes)
+      throw ArgError("amr_set_state_prim_noalloc: " + std::to_string(need) +
+                     " bytes of primitives and patch indices exceed its " +
+                     std::to_string(amr::StateIO::kScratchBytes) +
+                     "-byte scratch; split the patches over several calls");
+    if (!h->noalloc_scratch) throw StateError("no-allocation scratch not resolved");
+    char* base = (char*)h->noalloc_scratch;
+    double* d_prim = (double*)base;
+    long long* d_src = (long long*)(base + prim_bytes);
+    int* d_pids = (int*)(d_src + npatch);
+    HIP_OK(hipMemcpyAsync(d_prim, prim, (size_t)total * sizeof(double), hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipMemcpyAsync(d_src, src.data(), (size_t)npatch * sizeof(long long),
+                          hipMemcpyHostToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(d_pids, pids, (size_t)npatch * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
+    h->lam_valid = false;
+    amr::StateIO::set_prim(h->dm, h->U[buf], d_prim, d_src, d_pids, npatch,
+                           h->cfg.gamma - 1.0, h->stream);
+    h->check_launch();
+    h->sync();  // src lives on this host stack; the scratch is the next call's
     return AMR_OK;
   });
 }

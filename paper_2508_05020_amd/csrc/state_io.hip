@@ -5,6 +5,8 @@
 // produces.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #pragma clang fp contract(off)
 
 #include "device_common.hpp"
@@ -12,6 +14,17 @@
 
 namespace amr {
 namespace {
+
+// Staging memory of the upload that allocates nothing: every GPU the library
+// runs on holds one copy of this array until the process ends.  Host code
+// must not pass `scratch` itself to a kernel (in host code the name is a
+// host-side stand-in): it uses the device address hipGetSymbolAddress gives
+// for the current device, resolved once per device by noalloc_scratch().
+static __device__ __align__(256) unsigned char scratch[StateIO::kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 template <int D>
 __global__ __launch_bounds__(256) void k_set_prim(DevMesh m, double* __restrict__ U,
@@ -52,6 +65,23 @@ __global__ __launch_bounds__(256) void k_set_prim(DevMesh m, double* __restrict_
 }
 
 }  // namespace
+
+hipError_t StateIO::noalloc_scratch(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 void StateIO::set_prim(const DevMesh& m, double* U, const double* prim, const long long* src,
                        const int* pids, int count, double gm1, hipStream_t s) {
