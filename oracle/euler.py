@@ -199,6 +199,143 @@ def edge_fluxes(U: np.ndarray, d: int, j: int, gamma: float, eps: float,
     return rusanov(left[0], left[1], left[2:], right[0], right[1], right[2:], j, gamma)
 
 
+# ---------------------------------------------------------------------------
+# Characteristic-variable interpolation (shock-capturing variant, Section 2.2)
+# ---------------------------------------------------------------------------
+
+
+def mean_state(Ua, Ub):
+    """Arithmetic mean of two conserved states: the state at which the flux
+    Jacobian is decomposed for the edge between them."""
+    return [0.5 * (a + b) for a, b in zip(Ua, Ub)]
+
+
+def flux_eigenvectors(Ubar, d: int, j: int, gamma: float):
+    """Right eigenvectors (R[v][k]: component v of vector k) and left
+    eigenvectors (L[k][v], the rows of R^-1) of A_j = dF_j/dU, the Jacobian
+    of the direction-j flux of Eq. (1)-(3), at the conserved state Ubar.
+
+    Waves k in the order u_j - c, u_j (entropy), u_j (one shear wave per
+    tangential direction, ascending), u_j + c.  With u = m / rho,
+    q2 = u.u, p = (gamma - 1)(E - rho q2 / 2), c^2 = gamma p / rho,
+    H = (E + p) / rho, b1 = (gamma - 1) / c^2 and b2 = b1 q2 / 2:
+      r_- = (1, u - c e_j, H - u_j c),   r_e = (1, u, q2 / 2),
+      r_t = (0, e_t, u_t),               r_+ = (1, u + c e_j, H + u_j c);
+      l_- = ((b2 + u_j / c) / 2, -(b1 u + e_j / c) / 2, b1 / 2),
+      l_e = (1 - b2, b1 u, -b1),          l_t = (-u_t, e_t, 0),
+      l_+ = ((b2 - u_j / c) / 2, -(b1 u - e_j / c) / 2, b1 / 2).
+    """
+    nv = d + 2
+    rho = Ubar[0]
+    u = [Ubar[1 + i] / rho for i in range(d)]
+    q2 = u[0] * u[0]
+    for i in range(1, d):
+        q2 = q2 + u[i] * u[i]
+    p = (gamma - 1.0) * (Ubar[d + 1] - 0.5 * rho * q2)
+    c = np.sqrt(gamma * p / rho)
+    H = (Ubar[d + 1] + p) / rho
+    b1 = (gamma - 1.0) / (c * c)
+    b2 = 0.5 * b1 * q2
+    zero = np.zeros_like(rho)
+    one = np.ones_like(rho)
+    tang = [t for t in range(d) if t != j]
+    R = [[None] * nv for _ in range(nv)]
+    L = [[None] * nv for _ in range(nv)]
+    # columns of R
+    cols = []
+    cols.append([one] + [u[i] - c if i == j else u[i] for i in range(d)] + [H - u[j] * c])
+    cols.append([one] + [u[i] for i in range(d)] + [0.5 * q2])
+    for t in tang:
+        cols.append([zero] + [one if i == t else zero for i in range(d)] + [u[t]])
+    cols.append([one] + [u[i] + c if i == j else u[i] for i in range(d)] + [H + u[j] * c])
+    for k in range(nv):
+        for v in range(nv):
+            R[v][k] = cols[k][v]
+    # rows of L
+    rows = []
+    rows.append([0.5 * (b2 + u[j] / c)]
+                + [-0.5 * (b1 * u[i] + (1.0 / c if i == j else 0.0)) for i in range(d)]
+                + [0.5 * b1])
+    rows.append([1.0 - b2] + [b1 * u[i] for i in range(d)] + [-b1])
+    for t in tang:
+        rows.append([-u[t]] + [one if i == t else zero for i in range(d)] + [zero])
+    rows.append([0.5 * (b2 - u[j] / c)]
+                + [-0.5 * (b1 * u[i] - (1.0 / c if i == j else 0.0)) for i in range(d)]
+                + [0.5 * b1])
+    for k in range(nv):
+        for v in range(nv):
+            L[k][v] = rows[k][v]
+    return R, L
+
+
+def _matvec(M, x):
+    """sum_v M[k][v] x[v] for every k, terms added in v order."""
+    out = []
+    for row in M:
+        acc = row[0] * x[0]
+        for v in range(1, len(x)):
+            acc = acc + row[v] * x[v]
+        out.append(acc)
+    return out
+
+
+def physical_flux(U, d: int, j: int, gamma: float):
+    """F_j(U) of Eq. (1)-(3) from conserved values, and |u_j| + c."""
+    rho = U[0]
+    u = [U[1 + i] / rho for i in range(d)]
+    q2 = u[0] * u[0]
+    for i in range(1, d):
+        q2 = q2 + u[i] * u[i]
+    p = (gamma - 1.0) * (U[d + 1] - 0.5 * rho * q2)
+    F = [U[1 + j]] + [U[1 + i] * u[j] + (p if i == j else 0.0) for i in range(d)] \
+        + [(U[d + 1] + p) * u[j]]
+    return F, np.abs(u[j]) + np.sqrt(gamma * p / rho)
+
+
+def rusanov_conserved(UL, UR, d: int, j: int, gamma: float):
+    """Eq. (11) with the wave speed of Eq. (12), from conserved edge states."""
+    FL, sl = physical_flux(UL, d, j, gamma)
+    FR, sr = physical_flux(UR, d, j, gamma)
+    S = np.maximum(sr, sl)
+    return [0.5 * (FR[v] + FL[v]) - 0.5 * S * (UR[v] - UL[v]) for v in range(d + 2)]
+
+
+def edge_fluxes_characteristic(U: np.ndarray, d: int, j: int, gamma: float, eps: float,
+                               ng: int = NG):
+    """Riemann fluxes at the edges i+1/2, i = -2 .. n, along direction j, from
+    characteristic variables: the conserved states of the window nodes
+    i-2 .. i+3 are projected on the left eigenvectors of A_j at the mean of
+    nodes i and i+1, each characteristic field is interpolated by WENO5-JS
+    (left value from nodes i-2..i+2, right value from the mirrored stencil
+    i+3..i-1), and the values are projected back with the right
+    eigenvectors.  An edge where an interpolated rho or p is not positive on
+    either side falls back to first order (the conserved states of nodes i
+    and i+1)."""
+    n = U.shape[1] - 2 * ng
+    nv = d + 2
+    Uc = [_interior_cross(U[v], d, j, n, ng) for v in range(nv)]
+    ax = axis_of(j, d) - 1
+    ne = n + 3
+    s = [[_shift(Uc[v], ax, ng - 4 + k, ne) for v in range(nv)] for k in range(6)]
+    R, L = flux_eigenvectors(mean_state(s[2], s[3]), d, j, gamma)
+    W = [_matvec(L, s[k]) for k in range(6)]
+    WL = [weno5js(W[0][k], W[1][k], W[2][k], W[3][k], W[4][k], eps) for k in range(nv)]
+    WR = [weno5js(W[5][k], W[4][k], W[3][k], W[2][k], W[1][k], eps) for k in range(nv)]
+    UL = _matvec(R, WL)
+    UR = _matvec(R, WR)
+    ok = np.ones(UL[0].shape, dtype=bool)
+    for X in (UL, UR):
+        rho = X[0]
+        ke = X[1] * (X[1] / rho)
+        for i in range(1, d):
+            ke = ke + X[1 + i] * (X[1 + i] / rho)
+        p = (gamma - 1.0) * (X[d + 1] - 0.5 * ke)
+        ok &= (rho > 0.0) & (p > 0.0)
+    UL = [np.where(ok, a, b) for a, b in zip(UL, s[2])]
+    UR = [np.where(ok, a, b) for a, b in zip(UR, s[3])]
+    return rusanov_conserved(UL, UR, d, j, gamma)
+
+
 def face_fluxes(F, d: int, j: int):
     """Conservative face flux G at faces -1/2 .. n-1/2 from the edge fluxes
     at i+1/2, i = -2..n:  G_{i+1/2} = F_{i+1/2} - (F_{i-1/2} - 2 F_{i+1/2} + F_{i+3/2}) / 24.
@@ -222,8 +359,11 @@ def patch_faces(U: np.ndarray, d: int, gamma: float, eps: float, ng: int = NG,
                 scheme: str = "weno"):
     """Face fluxes G of every direction: list over j of arrays [v, ...] with
     n+1 faces along direction j and n interior lines in the others."""
-    return [np.stack(face_fluxes(edge_fluxes(U, d, j, gamma, eps, ng, scheme), d, j))
-            for j in range(d)]
+    def edges(j):
+        if scheme == "char":
+            return edge_fluxes_characteristic(U, d, j, gamma, eps, ng)
+        return edge_fluxes(U, d, j, gamma, eps, ng, scheme)
+    return [np.stack(face_fluxes(edges(j), d, j)) for j in range(d)]
 
 
 def divergence(faces, d: int, h: float) -> np.ndarray:
