@@ -7,7 +7,7 @@ combine + coarse/fine flux correction + restriction), plus the gradient tag
 and regrid every ``regrid_interval`` steps, on seeded synthetic data already
 resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--exec batched|per_patch]
+    python bench.py [--steps K] [--warmup W] [--config c5] [--exec batched|per_patch]
 """
 from __future__ import annotations
 
@@ -81,33 +81,120 @@ def measured_traffic(variant, cells_per_launch):
     return (v["fetch_bytes_per_cell"] + v["write_bytes_per_cell"]) * cells_per_launch
 
 
-# largest base grid whose initial hierarchy the oracle steps within about a
-# minute on one host core (2D 512^2)
+# largest 2D base grid whose initial hierarchy the oracle steps within about a
+# minute on one host core (512^2)
 ORACLE_MAX_BASE_CELLS = 1 << 18
 
 
+def host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown CPU"
+
+
 def cpu_baseline(cfg, seed: int):
-    """The oracle, as it stands, on a bounded sample: one SSP-RK3 step over the
-    initial hierarchy of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the workload: one
+    SSP-RK3 step over a hierarchy it builds itself from the same generator
+    and seed.  In 3D the sample is the benchmark layout (patches 32/16/16/8,
+    4 levels) on a 64^3 base, refined around the first blast so that every
+    level has coarse/fine faces (about 750 k leaf cells); in 1D and 2D it
+    is the workload's own initial hierarchy.  numpy, one thread."""
     from paper_2508_05020_amd import workloads
     from oracle.solver import OracleAMR
-    o = OracleAMR(cfg)
-    o.init_from_ic(workloads.initial_data(cfg, seed))
+    gen = workloads.initial_data(cfg, seed)
+    if cfg.dim == 3:
+        sc = workloads.c5_sample_config().replace(ic=cfg.ic, cfl=cfg.cfl, gamma=cfg.gamma)
+        o = OracleAMR(sc)
+        for k in o.forest.keys():
+            o.set_initial(k, gen)
+        for keys in workloads.blast_refinements(sc, seed):
+            o.regrid(keys, [], gen)
+        what = (f"one SSP-RK3 step of the oracle on the {cfg.name} layout (patches "
+                f"{sc.patch_cells}, {sc.max_levels} levels) over a {sc.base_cells}^3 base "
+                f"refined around the first blast of the same generator ({cfg.ic}, seed {seed})")
+    elif cfg.base_cells ** cfg.dim <= ORACLE_MAX_BASE_CELLS:
+        o = OracleAMR(cfg)
+        o.init_from_ic(gen)
+        what = f"one SSP-RK3 step of the oracle over the {cfg.name} initial hierarchy (seed {seed})"
+    else:
+        return None
     cells = o.leaf_cells()
     t0 = time.perf_counter()
     o.step()
     dt = time.perf_counter() - t0
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one SSP-RK3 step of the {cfg.name} initial hierarchy "
-                      f"({cells} leaf cells, seed {seed}), numpy FP64, single thread, "
-                      f"{dt:.1f} s"}
+            "sample": f"{what}: {cells} leaf cells in {dt:.1f} s; numpy FP64, single thread, "
+                      f"{host_cpu()}"}
 
 
-def copy_calibration() -> int:
-    """10 copies of 1 GiB between two device buffers: a kernel whose HBM
-    traffic is known (1 GiB read + 1 GiB written per launch)."""
+def _counter_csv(path: str, kernel: str, counter: str):
+    """Per-dispatch values of one counter for the kernels whose name contains
+    `kernel`, in dispatch order, from a rocprofv3 counter_collection CSV."""
+    import csv
+    vals = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                d = int(r["Dispatch_Id"])
+                vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+    return [vals[d] for d in sorted(vals)]
+
+
+def ingest_counters(args) -> int:
+    """Write profiles/k_stage_counters.json from rocprofv3 counter runs: the
+    stage kernel's FETCH_SIZE and WRITE_SIZE per dispatch (KiB) on a run of
+    `bench.py --no-autotune --tile T` whose first steps do not regrid (every
+    dispatch covers the log's leaf cells), scaled by what the same counters
+    read for device copies of known size."""
+    import re
+    d = args.ingest_counters
+    tile = args.tile
+    with open(os.path.join(d, "s_fetch.log")) as f:
+        log_text = f.read()
+    cells = int(re.search(r"stage kernel: \d+ launches over \d+ steps, [\d.]+ ms, (\d+) leaf cells",
+                          log_text).group(1))
+    workload = re.search(r"\[bench\] (\S+): initial hierarchy", log_text).group(1)
+    gib = args.copy_gib
+    cal_f = _counter_csv(os.path.join(d, "cal_fetch", "run_counter_collection.csv"),
+                         "copyBuffer", "FETCH_SIZE")
+    cal_w = _counter_csv(os.path.join(d, "cal_write", "run_counter_collection.csv"),
+                         "copyBuffer", "WRITE_SIZE")
+    copy_kib = gib * 1024 * 1024
+    sf = copy_kib / (sum(cal_f) / len(cal_f))
+    sw = copy_kib / (sum(cal_w) / len(cal_w))
+    fetch = _counter_csv(os.path.join(d, "s_fetch", "run_counter_collection.csv"), "k_stage",
+                         "FETCH_SIZE")
+    write = _counter_csv(os.path.join(d, "s_write", "run_counter_collection.csv"), "k_stage",
+                         "WRITE_SIZE")
+    rec = {"kernel": "k_stage", "workload": workload, "leaf_cells_per_dispatch": cells,
+           "dispatches": len(fetch), "source_sha256": kernel_source_hash(),
+           "scale": {"fetch": sf, "write": sw, "copy_gib": gib},
+           "variants": {str(tile): {
+               "fetch_bytes_per_cell": sum(fetch) / len(fetch) * 1024 * sf / cells,
+               "write_bytes_per_cell": sum(write) / len(write) * 1024 * sw / cells,
+               "fetch_bytes_per_cell_by_stage": [
+                   sum(fetch[k::3]) / len(fetch[k::3]) * 1024 * sf / cells for k in range(3)],
+               "write_bytes_per_cell_by_stage": [
+                   sum(write[k::3]) / len(write[k::3]) * 1024 * sw / cells for k in range(3)]}},
+           "commands": "see k_stage_c5.md"}
+    with open(COUNTERS, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
+    return 0
+
+
+def copy_calibration(gib: int = 1) -> int:
+    """10 copies of ``gib`` GiB between two device buffers: a kernel whose
+    HBM traffic is known (gib GiB read + gib GiB written per launch)."""
     import torch
-    n = 1 << 27  # float64 elements = 1 GiB
+    n = gib << 27  # float64 elements
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -121,138 +208,173 @@ def copy_calibration() -> int:
     return 0
 
 
-def learned_gain(args) -> int:
-    """Train the refinement predictor on the solver's own tags, then compare
-    regridding policies on one seeded run (2D quadrants + blobs, or 3D blast
-    waves + density perturbations): wall-clock per unit simulated time, judge
-    failures (fallbacks), regrids and cell updates.  Every policy runs under
-    the plain-tag judge with fallback, so all advance on meshes that cover the
-    plain tags at the same rate."""
-    import numpy as np
+def train_predictor(dim: int, horizon: int, buffer: int, runs: int, epochs: int,
+                    recall: float, seed_eval: int, base: int, n: int = None):
+    """Train the refinement predictor on the solver's own tags: single-level
+    periodic runs of the workload's generator (2D quadrants + blobs on 16^2
+    patches, 3D blasts + perturbations on 8^3 tiles) at resolutions base and
+    2 base, labels = the plain tagger's dilated tags over the next
+    ``horizon`` steps.  Returns the trained weights and what the comparison
+    needs (normalisation, tau for ``recall`` of the held-out patches)."""
     from paper_2508_05020_amd import amr, learned, workloads
-
-    H, b, dim = args.learned_every, args.learned_buffer, args.learned_dim
-    seed_eval = args.seed_eval if args.seed_eval is not None else (4100 if dim == 2 else 5100)
-    rounds = args.learned_rounds if args.learned_rounds is not None else (1 if dim == 2 else 2)
-    if dim == 2:
-        # the patch edge of the evaluation workload when one is named (the 2D
-        # network predicts leaves of one edge), else 16
-        n = 16
-        if args.learned_eval:
-            edges = set(workloads.config(args.learned_eval).patch_cells)
-            if len(edges) != 1:
-                raise SystemExit("the 2D network needs one patch edge on every level")
-            n = edges.pop()
-        cfg = workloads.AMRConfig(name="quadrants-blobs-4lev", dim=2, base_cells=max(64, 2 * n),
-                                  patch_cells=[n] * 4, periodic=[True, True],
-                                  ic="quadrants_blobs", tag_buffer=b, max_patches=16384)
-        seeds = list(range(4000, 4000 + args.train_runs))
-        stride = 2
-    else:
-        n = 8
-        cfg = workloads.AMRConfig(name="blasts-perturbed-4lev", dim=3, base_cells=16,
-                                  patch_cells=[n] * 4, periodic=[True] * 3,
-                                  ic="blasts_perturbed", tag_buffer=b, max_patches=32768)
-        seeds = list(range(5000, 5000 + args.train_runs))
-        stride = 4
-    res = tuple(cfg.base_cells * 2 ** l for l in range(cfg.max_levels))
+    if n is None:
+        n = 16 if dim == 2 else 8
+    seeds = list(range(4000 if dim == 2 else 5000, (4000 if dim == 2 else 5000) + runs))
+    res = (base, 2 * base)
     t0 = time.perf_counter()
     mean, std = learned.input_statistics(
-        [learned.uniform_config(cfg.base_cells, n, tag_buffer=b, dim=dim)], seeds[:1], steps=8)
-    data = learned.build_dataset(res, seeds, steps=40, horizon=H, stride=stride, mean=mean,
-                                 std=std, n=n, tag_buffer=b, dim=dim)
-    val = learned.build_dataset(res[-2:], [seed_eval], steps=40, horizon=H, stride=4,
-                                mean=mean, std=std, n=n, tag_buffer=b, dim=dim)
+        [learned.uniform_config(base, n, tag_buffer=buffer, dim=dim)], seeds[:1], steps=8)
+    data = learned.build_dataset(res, seeds, steps=32, horizon=horizon, stride=4, mean=mean,
+                                 std=std, n=n, tag_buffer=buffer, dim=dim)
+    val = learned.build_dataset(res, [seed_eval], steps=32, horizon=horizon, stride=4,
+                                mean=mean, std=std, n=n, tag_buffer=buffer, dim=dim)
+    data_s = time.perf_counter() - t0
     pos = float(data.y.mean())
     pos_weight = float(min(100.0, (1.0 - pos) / max(pos, 1e-6)))
     log(f"[learned] {data.x.shape[0]} training tiles from {len(seeds)} runs at {res}, "
-        f"positive cells {pos:.3f} ({time.perf_counter() - t0:.1f} s)")
+        f"positive cells {pos:.3f} ({data_s:.1f} s)")
+    cfg = learned.uniform_config(base, n, tag_buffer=buffer, dim=dim)
+    h = amr.Hierarchy(cfg)
+    pred = amr.Predictor(h, n, mean, std, pos_weight=pos_weight, max_batch=256)
+    pred.set_weights(learned.init_weights(seed=1, dim=dim))
+    t1 = time.perf_counter()
+    losses = learned.train(pred, data, epochs=epochs, lr=2e-3, batch=64)
+    train_s = time.perf_counter() - t1
+    tau = learned.choose_tau(pred, val, recall=recall)
+    met = learned.patch_metrics(pred, val, tau)
+    weights = pred.get_weights()
+    pred.close()
+    h.close()
+    log(f"[learned] trained in {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
+        f"tau {tau:.4f}, validation {met}")
+    return {"n": n, "mean": mean, "std": std, "pos_weight": pos_weight, "tau": tau,
+            "weights": weights,
+            "info": {"tiles": int(data.x.shape[0]), "runs": len(seeds),
+                     "resolutions": list(res), "horizon": horizon, "epochs": epochs,
+                     "first_loss": losses[0], "final_loss": losses[-1],
+                     "data_seconds": data_s, "train_seconds": train_s, "tau": tau,
+                     "recall_target": recall, "validation": met}}
 
-    # evaluation workload: the training configuration, or a named one (its
-    # dilation set to the one the labels were made with)
-    ecfg, eseed = cfg, seed_eval
+
+def compare_policies(ecfg, eseed: int, steps: int, policies, trained, rounds: int):
+    """Wall-clock per unit simulated time of regridding policies on one
+    workload, each from its own fresh initial hierarchy, all under the
+    plain-tag judge with fallback (every step covers the plain tags at the
+    workload's own dilation).  ``policies``: (name, every, kind, exec mode,
+    regrid dilation or None)."""
+    import torch
+    from paper_2508_05020_amd import amr, learned, workloads
+    results = {}
+    for name, every, kind, mode, buf in policies:
+        t0 = time.perf_counter()
+        h = amr.Hierarchy(ecfg, exec_mode=mode)
+        amr.init_from_ic(h, workloads.initial_data(ecfg, eseed))
+        pred = None
+        if kind == "learned":
+            pred = amr.Predictor(h, trained["n"], trained["mean"], trained["std"],
+                                 pos_weight=trained["pos_weight"], max_batch=256)
+            pred.set_weights(trained["weights"])
+            pred.predict(0, trained["tau"])  # first use of the kernels, outside the timing
+        torch.cuda.synchronize()
+        log(f"[learned] {name}: initial hierarchy in {time.perf_counter() - t0:.1f} s")
+        st = learned.run_policy(h, steps, every, kind, pred, trained["tau"] if pred else 0.5,
+                                judge=True, rounds=rounds, regrid_buffer=buf)
+        results[name] = st.as_dict()
+        log(f"[learned] {name}: {results[name]}")
+        if pred is not None:
+            pred.close()
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    return results
+
+
+def learned_gain(args) -> int:
+    """Train the refinement predictor on the solver's own tags, then compare
+    regridding policies on one seeded run: wall-clock per unit simulated
+    time, judge fallbacks, regrids, cell updates and coverage."""
+    import math
+    from paper_2508_05020_amd import amr, workloads
+    H, b, dim = args.learned_every, args.learned_buffer, args.learned_dim
+    seed_eval = args.seed_eval if args.seed_eval is not None else (4100 if dim == 2 else 5100)
+    rounds = args.learned_rounds if args.learned_rounds is not None else (1 if dim == 2 else 2)
+    n = None
+    if dim == 2 and args.learned_eval:
+        # the 2D network predicts leaves of one patch edge
+        edges = set(workloads.config(args.learned_eval).patch_cells)
+        if len(edges) != 1:
+            raise SystemExit("the 2D network needs one patch edge on every level")
+        n = edges.pop()
+    trained = train_predictor(dim, H, b, args.train_runs, args.epochs, args.recall, seed_eval,
+                              base=64 if dim == 2 else 32, n=n)
     if args.learned_eval:
         ecfg = workloads.config(args.learned_eval).replace(tag_buffer=b)
         if ecfg.dim != dim:
             raise SystemExit(f"--learned-eval {args.learned_eval} is {ecfg.dim}D, the network {dim}D")
         num = args.learned_eval[1:] if args.learned_eval[1:].isdigit() else "0"
         eseed = workloads.seed_for(int(num), 1)
-
-    def hier(mode=amr.EXEC_BATCHED, c=None, seed=None):
-        c = ecfg if c is None else c
-        h = amr.Hierarchy(c, exec_mode=mode)
-        amr.init_from_ic(h, workloads.initial_data(c, eseed if seed is None else seed))
-        return h
-
-    if not args.learned_eval:
-        h = hier()
-        learned.run_policy(h, 8, 2, "plain", judge=True)  # warm-up outside the comparison
-        h.close()
-    h_bl = hier() if not args.learned_eval else hier(c=cfg, seed=seed_eval)
-    pred = amr.Predictor(h_bl, n, mean, std, pos_weight=pos_weight, max_batch=256)
-    pred.set_weights(learned.init_weights(seed=1, dim=dim))
-    t1 = time.perf_counter()
-    losses = learned.train(pred, data, epochs=args.epochs, lr=2e-3, batch=64)
-    train_s = time.perf_counter() - t1
-    tau = learned.choose_tau(pred, val, recall=0.99)
-    met = learned.patch_metrics(pred, val, tau)
-    pred.predict(0, tau)  # first use of the inference kernels, outside the comparison
-    log(f"[learned] trained in {train_s:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}, "
-        f"tau {tau:.4f}, validation {met}")
-
+    else:
+        n = trained["n"]
+        ecfg = workloads.AMRConfig(
+            name=f"{'quadrants-blobs' if dim == 2 else 'blasts-perturbed'}-4lev", dim=dim,
+            base_cells=64 if dim == 2 else 16, patch_cells=[n] * 4, periodic=[True] * dim,
+            ic="quadrants_blobs" if dim == 2 else "blasts_perturbed", tag_buffer=b,
+            max_patches=16384 if dim == 2 else 32768)
+        eseed = seed_eval
+    wide = min(3, math.ceil(H * ecfg.cfl))
+    policies = [("P_plain2_per_patch", 2, "plain", amr.EXEC_PER_PATCH, None),
+                ("B_plain2", 2, "plain", amr.EXEC_BATCHED, None),
+                (f"B{H}_plain{H}_dilation{wide}", H, "plain", amr.EXEC_BATCHED, wide),
+                (f"BL_learned{H}", H, "learned", amr.EXEC_BATCHED, None)]
     if args.learned_eval:
-        # the evaluation hierarchy gets its own predictor with the trained
-        # weights; one large hierarchy at a time
-        weights = pred.get_weights()
-        pred.close()
-        h_bl.close()
-        import torch
-        torch.cuda.empty_cache()
-
-    results = {}
-    steps = args.steps
-    for name, every, policy, mode in (("plain2_per_patch", 2, "plain", amr.EXEC_PER_PATCH),
-                                      ("plain2", 2, "plain", amr.EXEC_BATCHED),
-                                      (f"plain{H}", H, "plain", amr.EXEC_BATCHED),
-                                      (f"learned{H}", H, "learned", amr.EXEC_BATCHED)):
-        if args.learned_eval and mode == amr.EXEC_PER_PATCH:
-            continue  # one launch per patch and phase: hours on a large workload
-        if policy == "learned" and args.learned_eval:
-            h = hier()
-            pred = amr.Predictor(h, n, mean, std, pos_weight=pos_weight, max_batch=256)
-            pred.set_weights(weights)
-            pred.predict(0, tau)
-        else:
-            h = h_bl if policy == "learned" else hier(mode)
-        st = learned.run_policy(h, steps, every, policy, pred if policy == "learned" else None,
-                                tau, judge=True, rounds=rounds)
-        results[name] = st.as_dict()
-        log(f"[learned] {name}: {results[name]}")
-        if policy != "learned":
-            h.close()
-            if args.learned_eval:
-                import torch
-                torch.cuda.empty_cache()
-    L = results[f"learned{H}"]["wall_per_tsim"]
-    desc = (f"{ecfg.name}: {dim}D base {ecfg.base_cells}^{dim}, {ecfg.max_levels} levels of "
-            f"{ecfg.patch_cells} patches, dilation {b}, seed {eseed}, {steps} steps")
-    if args.learned_eval:
-        desc += (f"; network trained on {cfg.name} ({dim}D base {cfg.base_cells}^{dim}, "
-                 f"{n}^{dim} patches)")
+        policies = policies[1:]  # one launch per patch and phase: hours on a large workload
+    results = compare_policies(ecfg, eseed, args.steps, policies, trained, rounds)
+    L = results[f"BL_learned{H}"]["wall_per_tsim"]
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
-           "config": {"workload": desc},
-           "learned_rounds": rounds,
-           "training": {"tiles": int(data.x.shape[0]), "runs": len(seeds), "horizon": H,
-                        "epochs": args.epochs, "first_loss": losses[0], "final_loss": losses[-1],
-                        "seconds": train_s, "tau": tau, "validation": met},
-           "policies": results,
-           "gain_vs_plain2_per_patch": (results["plain2_per_patch"]["wall_per_tsim"] / L
-                                        if "plain2_per_patch" in results else None),
-           "gain_vs_plain2": results["plain2"]["wall_per_tsim"] / L,
-           f"gain_vs_plain{H}": results[f"plain{H}"]["wall_per_tsim"] / L}
+           "config": {"workload": f"{ecfg.name}: {dim}D base {ecfg.base_cells}^{dim}, "
+                                  f"{ecfg.max_levels} levels of {ecfg.patch_cells} patches, "
+                                  f"dilation {b}, seed {eseed}, {args.steps} steps"},
+           "learned_rounds": rounds, "training": trained["info"], "policies": results,
+           "gain_vs": {k: v["wall_per_tsim"] / L for k, v in results.items()}}
     print(json.dumps(out), flush=True)
-    pred.close()
     return 0
+
+
+def learned_vs_plain(cfg, args):
+    """The metric's third part on the benchmark workload itself: the
+    predictor trained on the generator's own tags, then batched plain
+    regridding every 2 steps (B), batched plain regridding at the workload's
+    interval with the dilation widened to ceil(interval x CFL) (at most 3,
+    B8), and batched learned regridding at that interval (BL), each for
+    ``--learned-steps`` steps from a fresh initial hierarchy under the
+    plain-tag judge, so that every policy runs at the same (full) coverage
+    of the plain tags.  The per-patch policy is not run on this workload (one
+    launch per patch and phase)."""
+    import math
+    from paper_2508_05020_amd import amr
+    H = cfg.regrid_interval
+    t0 = time.perf_counter()
+    if cfg.dim == 2 and len(set(cfg.patch_cells)) != 1:
+        return None  # the 2D network predicts leaves of one patch edge
+    trained = train_predictor(cfg.dim, H, cfg.tag_buffer, args.train_runs, args.epochs,
+                              args.recall, 5100 if cfg.dim == 3 else 4100,
+                              base=32 if cfg.dim == 3 else 128,
+                              n=8 if cfg.dim == 3 else cfg.patch_cells[0])
+    wide = min(3, math.ceil(H * cfg.cfl))
+    policies = [("B_plain2", 2, "plain", amr.EXEC_BATCHED, None),
+                (f"B{H}_plain{H}_dilation{wide}", H, "plain", amr.EXEC_BATCHED, wide),
+                (f"BL_learned{H}", H, "learned", amr.EXEC_BATCHED, None)]
+    res = compare_policies(cfg, args.seed, args.learned_steps, policies, trained,
+                           rounds=2 if cfg.dim == 3 else 1)
+    L = res[f"BL_learned{H}"]["wall_per_tsim"]
+    return {"unit": "s wall per unit simulated time", "steps": args.learned_steps,
+            "policies": {k: {"wall_per_tsim": v["wall_per_tsim"], "coverage": v["coverage"],
+                             "regrids": v["regrids"], "fallbacks": v["fallbacks"],
+                             "cell_updates": v["cell_updates"], "t_sim": v["t_sim"]}
+                         for k, v in res.items()},
+            "learned_speedup_vs": {k: v["wall_per_tsim"] / L for k, v in res.items()},
+            "training": trained["info"],
+            "seconds": time.perf_counter() - t0}
 
 
 def diag_bench(args) -> int:
@@ -297,9 +419,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps (default: the workload's configured run length, "
-                         "500 for c2; 128 for --learned; 50 calls for --diag)")
+                         "200 for c5; 128 for --learned; 50 calls for --diag)")
     ap.add_argument("--warmup", type=int, default=8)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--base", type=int, default=None,
+                    help="level-0 cells per dimension instead of the workload's (a smaller "
+                         "hierarchy of the same layout and generator)")
     ap.add_argument("--seed", type=int, default=None,
                     help="initial-data seed (default: 1000 * config number + 1)")
     ap.add_argument("--exec", dest="exec_mode", default="batched", choices=["batched", "per_patch"])
@@ -314,9 +439,9 @@ def main() -> int:
                     help="use this stage-kernel tile variant instead of autotuning")
     ap.add_argument("--learned", action="store_true",
                     help="train the refinement predictor and compare regrid policies")
-    ap.add_argument("--learned-every", type=int, default=16,
+    ap.add_argument("--learned-every", type=int, default=8,
                     help="regrid interval of the learned policy (and forecast horizon)")
-    ap.add_argument("--learned-buffer", type=int, default=1, help="tag dilation in cells")
+    ap.add_argument("--learned-buffer", type=int, default=2, help="tag dilation in cells")
     ap.add_argument("--diag", action="store_true",
                     help="time the velocity-gradient diagnostic instead of the step")
     ap.add_argument("--learned-rounds", type=int, default=None,
@@ -329,13 +454,27 @@ def main() -> int:
                     help="2D quadrants + blobs or 3D blast waves + perturbations")
     ap.add_argument("--seed-eval", type=int, default=None,
                     help="seed of the evaluation run (default 4100 in 2D, 5100 in 3D)")
-    ap.add_argument("--train-runs", type=int, default=3)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--train-runs", type=int, default=16,
+                    help="seeded single-level runs the predictor is trained on")
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--recall", type=float, default=0.995,
+                    help="fraction of held-out patches with a future tag the mask must flag")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-versus-plain regridding comparison of the default run")
+    ap.add_argument("--learned-steps", type=int, default=24,
+                    help="steps per policy in the default run's regridding comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales HBM counters)")
+    ap.add_argument("--copy-gib", type=int, default=1, help="size of each calibration copy")
+    ap.add_argument("--ingest-counters", default=None, metavar="DIR",
+                    help="write profiles/k_stage_counters.json from rocprofv3 counter runs in "
+                         "DIR (s_fetch/, s_write/, cal_fetch/, cal_write/ and s_fetch.log; "
+                         "--tile names the profiled variant)")
     args = ap.parse_args()
     if args.copy_calibration:
-        return copy_calibration()
+        return copy_calibration(args.copy_gib)
+    if args.ingest_counters:
+        return ingest_counters(args)
     if args.learned:
         if args.steps is None:
             args.steps = 128
@@ -354,6 +493,9 @@ def main() -> int:
     from paper_2508_05020_amd import amr, workloads
 
     cfg = workloads.config(args.config)
+    if args.base is not None:
+        cfg = cfg.replace(name=f"{cfg.name}-base{args.base}", base_cells=args.base)
+        cfg.validate()
     if args.steps is None:
         args.steps = cfg.steps
     if args.seed is None:
@@ -486,17 +628,19 @@ def main() -> int:
             "whole_step_frac": cells * b_step / elapsed / 1e9 / HBM_PEAK_GBS,
         },
     }
-    if not args.no_cpu_baseline:
-        if cfg.base_cells ** cfg.dim > ORACLE_MAX_BASE_CELLS:
-            # one oracle step over this initial hierarchy would take hours
-            out["cpu_baseline"] = None
-            log(f"[bench] no cpu_baseline: {cfg.base_cells}^{cfg.dim} base cells is beyond the "
-                f"oracle's bounded sample ({ORACLE_MAX_BASE_CELLS})")
-        else:
-            log("[bench] timing the oracle on a bounded sample")
-            out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
-    print(json.dumps(out), flush=True)
     h.close()
+    del h
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+        if out["cpu_baseline"] is None:
+            log(f"[bench] no cpu_baseline: {cfg.base_cells}^{cfg.dim} base cells is beyond the "
+                f"oracle's bounded sample")
+    if not args.no_learned and mode == amr.EXEC_BATCHED and cfg.dim >= 2 \
+            and cfg.regrid_interval > 2:
+        out["learned_vs_plain"] = learned_vs_plain(cfg, args)
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -54,7 +54,11 @@ typedef enum {
 enum { AMR_MAX_LEVELS = 8, AMR_GHOST = 4 };
 enum { AMR_EXEC_PER_PATCH = 0, AMR_EXEC_BATCHED = 1 };
 enum { AMR_COARSEN_TEXT = 0, AMR_COARSEN_LITERAL = 1 };
-enum { AMR_SCHEME_WENO = 0, AMR_SCHEME_CENTRAL = 1 };
+/* Interpolation of the edge states (Section 2.2): WENO5-JS on the primitive
+ * set (p, T, u_j); the 4th-order central interpolation of Eq. (8) (shock-free
+ * flows); WENO5-JS on characteristic variables (the eigenvectors of the
+ * direction's flux Jacobian at the mean of the two nodes beside the edge). */
+enum { AMR_SCHEME_WENO = 0, AMR_SCHEME_CENTRAL = 1, AMR_SCHEME_CHAR = 2 };
 
 /* Optional device allocator (e.g. a framework's caching allocator).  alloc
  * returns device memory of at least `bytes` bytes aligned to 256 B, or NULL. */
@@ -82,7 +86,7 @@ typedef struct {
   int level_capacity[AMR_MAX_LEVELS];/* slots per level; 0 = derive from max_patches */
   int exec_mode;                     /* AMR_EXEC_PER_PATCH or AMR_EXEC_BATCHED */
   int coarsen_rule;                  /* AMR_COARSEN_TEXT (default) or _LITERAL */
-  int scheme;                        /* AMR_SCHEME_WENO (default) or _CENTRAL */
+  int scheme;                        /* AMR_SCHEME_WENO (default), _CENTRAL or _CHAR */
 } amr_config;
 
 /* One row of the patch table (Fig. grid-meta of the paper: level, nbr,
@@ -255,6 +259,11 @@ amr_status amr_profile_read(amr_hierarchy* h, double* total_ms, int* launches, i
  * finest level that the gradient tagger would refine now on U^n (0 = the
  * current mesh covers every tag). */
 amr_status amr_judge(amr_hierarchy* h, int* uncovered);
+
+/* Tag dilation (amr_config.tag_buffer, 0..3 cells) for the following tag,
+ * adapt and judge calls (no device work); AMR_E_ARG outside 0..3.  Lets a
+ * caller regrid with a wider dilation than its judge checks coverage with. */
+amr_status amr_set_tag_buffer(amr_hierarchy* h, int cells);
 
 /* Execution mode switch (AMR_EXEC_PER_PATCH launches one kernel per patch per
  * phase; AMR_EXEC_BATCHED launches each phase once over all patches). */

@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 MAX_LEVELS = 8
 EXEC_PER_PATCH, EXEC_BATCHED = 0, 1
 COARSEN_TEXT, COARSEN_LITERAL = 0, 1
-SCHEME_WENO, SCHEME_CENTRAL = 0, 1
+SCHEME_WENO, SCHEME_CENTRAL, SCHEME_CHAR = 0, 1, 2
 NOALLOC_SCRATCH_BYTES = 32 << 20   # AMR_NOALLOC_SCRATCH_BYTES
 
 STATUS = {0: "AMR_OK", -1: "AMR_E_ARG", -2: "AMR_E_CAPACITY", -3: "AMR_E_HIP",
@@ -115,6 +115,7 @@ _sigs = {
     "amr_cnn_mfma_selftest": [_H, C.c_void_p, C.c_void_p, C.c_void_p],
     "amr_judge": [_H, _P(C.c_int)],
     "amr_set_fused_halo": [_H, C.c_int],
+    "amr_set_tag_buffer": [_H, C.c_int],
     "amr_set_graph": [_H, C.c_int],
     "amr_set_tile_variant": [_H, C.c_int],
     "amr_get_tile_variant": [_H, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)],
@@ -436,6 +437,9 @@ class Hierarchy:
     def set_fused_halo(self, enable: bool):
         self._ok(_lib.amr_set_fused_halo(self.h, 1 if enable else 0))
 
+    def set_tag_buffer(self, cells: int):
+        self._ok(_lib.amr_set_tag_buffer(self.h, int(cells)))
+
     def judge(self) -> int:
         n = C.c_int()
         self._ok(_lib.amr_judge(self.h, C.byref(n)))
@@ -569,12 +573,30 @@ def patch_primitives(cfg, level: int, coord, gen) -> np.ndarray:
     return np.stack([rho] + list(u) + [p])
 
 
+def upload_initial(h: Hierarchy, rows, gen, chunk_values: int = 1 << 23):
+    """Interior primitives of the given patch-table rows sampled from ``gen``
+    and uploaded, a level's patches evaluated together in chunks of about
+    ``chunk_values`` cells (the generators take stacked patch grids)."""
+    from . import workloads
+    cfg = h.cfg
+    by_level: Dict[int, list] = {}
+    for r in rows:
+        by_level.setdefault(r["level"], []).append(r)
+    for level, rs in sorted(by_level.items()):
+        per = max(1, chunk_values // cfg.patch_cells[level] ** cfg.dim)
+        for a in range(0, len(rs), per):
+            part = rs[a:a + per]
+            pts = workloads.patch_points_batch(cfg, level, [r["coord"] for r in part])
+            rho, u, p = gen(pts)
+            h.set_state_prim(0, {r["pid"]: np.stack([rho[i]] + [uj[i] for uj in u] + [p[i]])
+                                 for i, r in enumerate(part)})
+
+
 def init_from_ic(h: Hierarchy, gen) -> int:
     """Level-0 data from ``gen``, then max_levels-1 rounds of tag and refine
     with new patches sampled from ``gen``.  Returns the number of rounds."""
     cfg = h.cfg
-    table = h.patch_table()
-    h.set_state_prim(0, {r["pid"]: patch_primitives(cfg, r["level"], r["coord"], gen) for r in table})
+    upload_initial(h, h.patch_table(), gen)
     rounds = 0
     for _ in range(cfg.max_levels - 1):
         refine, _, _ = h.tag(0)
@@ -583,8 +605,6 @@ def init_from_ic(h: Hierarchy, gen) -> int:
             break
         h.regrid(r, np.zeros_like(r))
         new = set(h.last_created())
-        table = h.patch_table()
-        h.set_state_prim(0, {t["pid"]: patch_primitives(cfg, t["level"], t["coord"], gen)
-                             for t in table if t["pid"] in new})
+        upload_initial(h, [t for t in h.patch_table() if t["pid"] in new], gen)
         rounds += 1
     return rounds

@@ -227,6 +227,8 @@ void validate_config(const amr_config& c) {
   if (!(c.gamma > 1.0)) throw ArgError("gamma must exceed 1");
   if (!(c.cfl > 0.0)) throw ArgError("cfl must be positive");
   if (c.tag_buffer < 0 || c.tag_buffer > 3) throw ArgError("tag_buffer must be in 0..3");
+  if (c.scheme != AMR_SCHEME_WENO && c.scheme != AMR_SCHEME_CENTRAL && c.scheme != AMR_SCHEME_CHAR)
+    throw ArgError("scheme must be AMR_SCHEME_WENO, _CENTRAL or _CHAR");
   if (c.max_patches <= 0) throw ArgError("max_patches must be positive");
   for (int l = 0; l < c.max_levels; ++l) {
     const int n = c.patch_cells[l];
@@ -539,10 +541,29 @@ void sync_tables(amr_hierarchy* h, bool full) {
     h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
   }
   HIP_OK(hipMemcpyAsync(h->d_active_leaf, sa, mp, hipMemcpyHostToDevice, h->stream));
+  // coarse/fine faces of coarse-side leaves, then the faces whose flux
+  // registers refluxing reads: those coarse faces, and every face of a leaf
+  // across which no same-level patch lies inside the domain (a fine-side
+  // face of a coarse/fine interface, by R2); the stage kernel writes only
+  // these registers
   uint8_t* sm = sa + mp;
-  std::fill(sm, sm + mp, (uint8_t)0);
+  std::fill(sm, sm + 2 * mp, (uint8_t)0);
   for (int i = 0; i < nref; ++i) sm[L[r0 + 2 * i]] = (uint8_t)L[r0 + 2 * i + 1];
-  HIP_OK(hipMemcpyAsync(h->d_cfmask, sm, mp, hipMemcpyHostToDevice, h->stream));
+  uint8_t* sw = sm + mp;
+  for (int pid : order) {
+    if (!f.is_leaf(pid)) continue;
+    const int l = f.level[pid];
+    const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
+    int w = sm[pid];
+    for (int j = 0; j < f.dim; ++j)
+      for (int side = 0; side < 2; ++side) {
+        const int o = side ? 1 : -1;
+        if (f.neighbour(l, c, j == 0 ? o : 0, j == 1 ? o : 0, j == 2 ? o : 0) == -1)
+          w |= 1 << (2 * j + side);
+      }
+    sw[pid] = (uint8_t)w;
+  }
+  HIP_OK(hipMemcpyAsync(h->d_cfmask, sm, 2 * mp, hipMemcpyHostToDevice, h->stream));
   if (np > 0) {
     HIP_OK(hipMemcpyAsync(h->d_pairs, sp, pairs.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
@@ -807,7 +828,8 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->fr = (double*)h->dev_alloc(h->fr_doubles * sizeof(double));
     h->d_tab = (int*)h->dev_alloc(h->tab_ints * sizeof(int));
     h->d_active_leaf = (uint8_t*)h->dev_alloc(mp);
-    h->d_cfmask = (uint8_t*)h->dev_alloc(mp);
+    // per pid: coarse/fine face mask [0, mp), flux-register write mask [mp, 2 mp)
+    h->d_cfmask = (uint8_t*)h->dev_alloc(2 * mp);
     h->d_has_tag = (uint8_t*)h->dev_alloc(mp);
     h->d_refine = (uint8_t*)h->dev_alloc(mp);
     h->d_coarsen = (uint8_t*)h->dev_alloc(mp);
@@ -832,7 +854,7 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
     h->d_pairs = (int*)h->dev_alloc(h->pairs_cap * 2 * sizeof(int));
     h->h_stage_bytes = (size_t)h->lists_cap * sizeof(int) + (size_t)h->pairs_cap * 2 * sizeof(int) +
-                       2 * (size_t)mp + 256;
+                       3 * (size_t)mp + 256;
     HIP_OK(hipHostMalloc((void**)&h->h_stage, h->h_stage_bytes, hipHostMallocDefault));
     HIP_OK(hipHostMalloc((void**)&h->h_req, req_flag_offset(mp) + 64, hipHostMallocDefault));
     HIP_OK(hipMemsetAsync(h->d_has_tag, 0, mp, h->stream));
@@ -1292,6 +1314,18 @@ amr_status amr_autotune(amr_hierarchy* h, int reps, int* best, float* best_ms) {
     if (best_ms) *best_ms = win_ms;
     return AMR_OK;
   });
+}
+
+amr_status amr_set_tag_buffer(amr_hierarchy* h, int cells) {
+  if (!h) return AMR_E_ARG;
+  if (cells < 0 || cells > 3) {
+    h->err = "tag_buffer must be in 0..3";
+    return AMR_E_ARG;
+  }
+  h->cfg.tag_buffer = cells;
+  h->dm.tag_buffer = cells;
+  h->step_exec_valid = false;
+  return AMR_OK;
 }
 
 amr_status amr_set_fused_halo(amr_hierarchy* h, int enable) {

@@ -54,6 +54,23 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return fma(d, h, g);
 }
 
+// sqrt(x) and 1/sqrt(x) for x > 0 from the hardware reciprocal square-root
+// estimate: two coupled Goldschmidt steps for sqrt(x) and 1/(2 sqrt(x)),
+// then one Newton correction of the root (both within a few ulp).
+__device__ __forceinline__ void sqrt_rsqrt_nr(double x, double& s, double& is) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  s = fma(fma(-g, g, x), h, g);
+  is = 2.0 * h;
+}
+
 // Nonlinear WENO5-JS combination of three candidates from their smoothness
 // indicators.  The weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
 // t_k = (eps + beta_k)^2 and d = (1, 10, 5)/16 are evaluated as cross
@@ -157,8 +174,17 @@ struct TileShape {
   static constexpr int T1 = D >= 2 ? TY : 1;
   static constexpr int T2 = D >= 3 ? TZ : 1;
   static constexpr int NCELL = T0 * T1 * T2;
+  // Row pitch (doubles) of the node arrays in LDS: the union box of 1D/2D
+  // tiles and the x-extended box of 3D tiles have rows of T0 + 8 nodes, a
+  // multiple of 8 for the tile widths used; an odd pitch starts successive
+  // rows in different banks, so the lanes of a wave that read or write
+  // neighbouring rows do not collide.  The y- and z-extended 3D boxes are
+  // read in runs of whole rows and keep their width.
+  static constexpr int UPITCH = D == 1 ? T0 + 8 : ((T0 + 8) | 1);
+  static constexpr int NUNION = UPITCH * (D >= 2 ? T1 + 8 : 1);
+  static constexpr int xpitch(int j) { return j == 0 ? ((T0 + 8) | 1) : T0; }
   static constexpr int ext(int j) {
-    return (T0 + (j == 0 ? 8 : 0)) * (T1 + (j == 1 ? 8 : 0)) * (T2 + (j == 2 ? 8 : 0));
+    return xpitch(j) * (T1 + (j == 1 ? 8 : 0)) * (T2 + (j == 2 ? 8 : 0));
   }
   static constexpr int edges(int j) {
     return (T0 + (j == 0 ? 3 : 0)) * (T1 + (j == 1 ? 3 : 0)) * (T2 + (j == 2 ? 3 : 0));
@@ -185,12 +211,29 @@ __device__ __forceinline__ void node_primitives(const DevMesh& m, const double* 
   q[1] = p * r;
 }
 
+// What the edge phase reads of a node: its primitives (p, T, u_j), or for
+// the characteristic scheme its conserved values, at sP[k NEXT + idx].
+template <int D, bool CHAR>
+__device__ __forceinline__ void node_store(const DevMesh& m, const double* u, double* sP, int next,
+                                           int idx) {
+  if constexpr (CHAR) {
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) sP[v * next + idx] = u[v];
+  } else {
+    double q[D + 2];
+    node_primitives<D>(m, u, q);
+#pragma unroll
+    for (int k = 0; k < D + 2; ++k) sP[k * next + idx] = q[k];
+  }
+}
+
 // Same-level patches around the tile's patch, by offset code
-// (o0+1) + 3 (o1+1) + 9 (o2+1), o in {-1,0,1}^D (periodic wrap; -1 where no
-// patch or outside a non-periodic domain), looked up once per block.
+// (o0+1) + 3 (o1+1) + 9 (o2+1), o in {-1,0,1}^D (periodic wrap), as the
+// offsets of their data in the state buffer (-1 where no patch or outside a
+// non-periodic domain), looked up once per block.
 template <int D>
 __device__ __forceinline__ void load_neighbours(const DevMesh& m, int l, const int pc[3],
-                                                int* sN) {
+                                                long long* sNB) {
   constexpr int NO = D == 1 ? 3 : (D == 2 ? 9 : 27);
   const int t = threadIdx.x;
   if (t < NO) {
@@ -207,40 +250,44 @@ __device__ __forceinline__ void load_neighbours(const DevMesh& m, int l, const i
       }
       q[j] = v;
     }
-    sN[t] = in ? map_at<D>(m, l, q) : -1;
+    const int pid = in ? map_at<D>(m, l, q) : -1;
+    sNB[t] = pid >= 0 ? patch_base(m, pid, l) : -1;
   }
 }
 
-// Conserved values of a node at patch-local cell c (may lie in the halo):
-// from the patch itself, or by the ghost-fill rule when outside the patch
-// (same-level source from the neighbour table sN, else the patch's own ghost
-// layer, which holds the prolonged value).
+// Conserved values of a node at patch-local cell c (may lie in the halo,
+// at most 4 cells outside the patch): from the patch itself, or by the
+// ghost-fill rule when outside the patch (same-level source from the
+// neighbour table, where a position beyond a transmissive boundary is the
+// nearest cell of this patch, else the patch's own ghost layer, which holds
+// the prolonged value).
 template <int D, bool FUSE>
 __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* __restrict__ Uin,
                                                const double* __restrict__ Pin, int n, int full,
                                                const int c[3], const int pc[3], int l,
-                                               const int* sN, double* u) {
+                                               const long long* sNB, double* u) {
   constexpr int NV = D + 2;
   bool inside = true;
   for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
   const long long vs = var_stride<D>(full);
   if (FUSE && !inside) {
-    const LevelC& L = m.lv[l];
+    const int np = m.lv[l].np;
     int code = 0, loc[3] = {0, 0, 0}, mul = 1;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const int g = bc_map(pc[j] * n + c[j], L.cells, m.periodic[j]);
-      const int q = g / n;
-      int o = q - pc[j];
-      if (o > 1) o -= L.np;
-      if (o < -1) o += L.np;
-      loc[j] = g - q * n;
+      int o = c[j] < 0 ? -1 : (c[j] >= n ? 1 : 0);
+      int lj = c[j] - o * n;
+      if (o != 0 && !m.periodic[j] && (unsigned)(pc[j] + o) >= (unsigned)np) {
+        o = 0;
+        lj = c[j] < 0 ? 0 : n - 1;
+      }
+      loc[j] = lj;
       code += (o + 1) * mul;
       mul *= 3;
     }
-    const int src = sN[code];
-    if (src >= 0) {
-      const double* S = Uin + patch_base(m, src, l);
+    const long long sb = sNB[code];
+    if (sb >= 0) {
+      const double* S = Uin + sb;
       const long long off = box_off<D>(full, loc[0] + NG, loc[1] + NG, loc[2] + NG);
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = S[v * vs + off];
@@ -256,26 +303,24 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
 
 // 1D/2D: primitives of the tile plus 4-node halos in every direction
 // (corner nodes, used by no stencil, are skipped), loaded once per launch.
-template <int D, int TX, int TY, int NT, bool FUSE>
+template <int D, int TX, int TY, int NT, bool FUSE, bool CHAR>
 __device__ __forceinline__ void load_union(const DevMesh& m, const double* __restrict__ Uin,
                                            const double* __restrict__ Pin, int n, int full,
                                            const int o[3], const int pc[3], int l,
-                                           const int* sN, double* sP) {
+                                           const long long* sN, double* sP) {
+  using S = TileShape<D, TX, TY, 1>;
   constexpr int T0 = TX, T1 = D >= 2 ? TY : 1;
   constexpr int U0 = T0 + 8, U1 = D >= 2 ? T1 + 8 : 1;
   constexpr int NU = U0 * U1;
-  constexpr int NQ = D + 2;
   for (int idx = threadIdx.x; idx < NU; idx += NT) {
     const int e0 = idx % U0, e1 = idx / U0;
     const bool hx = e0 < 4 || e0 >= T0 + 4;
     const bool hy = D >= 2 && (e1 < 4 || e1 >= T1 + 4);
     if (hx && hy) continue;
     const int c[3] = {o[0] + e0 - 4, D >= 2 ? o[1] + e1 - 4 : 0, 0};
-    double u[D + 2], q[NQ];
+    double u[D + 2];
     node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u);
-    node_primitives<D>(m, u, q);
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) sP[k * NU + idx] = q[k];
+    node_store<D, CHAR>(m, u, sP, S::NUNION, e0 + S::UPITCH * e1);
   }
 }
 
@@ -333,23 +378,166 @@ __device__ __forceinline__ void edge_at_scheme(const DevMesh& m, const double* s
   }
 }
 
-// The scheme branch taken once per edge, so that each path is straight-line
-// code the compiler can schedule across the primitives.
+// Physical flux of direction J (Eq. (1)-(3)) of one conserved edge state
+// and its signal speed |u_J| + c (Eq. (7)), variable v of the flux in F[v].
+template <int D, int J>
+__device__ __forceinline__ void conserved_flux(const DevMesh& m, const double* U, double* F,
+                                               double& speed) {
+  const double ir = rcp_nr(U[0]);
+  double u[D];
+  double q2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    u[i] = U[1 + i] * ir;
+    q2 = (i == 0) ? u[0] * u[0] : fma(u[i], u[i], q2);
+  }
+  const double p = m.gm1 * fma(-0.5 * U[0], q2, U[D + 1]);
+  F[0] = U[1 + J];
+#pragma unroll
+  for (int i = 0; i < D; ++i) F[1 + i] = (i == J) ? fma(U[1 + i], u[J], p) : U[1 + i] * u[J];
+  F[D + 1] = (U[D + 1] + p) * u[J];
+  speed = sqrt_nr(m.gamma * p * ir) + fabs(u[J]);
+}
+
+// Riemann flux of direction J at one edge from characteristic variables (the
+// shock-capturing variant of Section 2.2): the conserved states of the
+// window nodes i-2 .. i+3 (in LDS, NEXT nodes per variable, STEP between
+// neighbours along J) are projected on the left eigenvectors of the flux
+// Jacobian A_J at the mean of nodes i and i+1, each characteristic field is
+// interpolated by WENO5-JS (left value from i-2..i+2, right value from the
+// mirrored stencil), and the edge states are projected back with the right
+// eigenvectors.  Fields in the order u_J - c, entropy, shear (tangential
+// directions ascending), u_J + c.  An edge where an interpolated rho or p is
+// not positive on either side takes the states of nodes i and i+1.  The
+// Rusanov flux (Eq. (11)-(12)) is stored doubled at sF[v NED + e].
 template <int D, int J, int NEXT, int STEP, int NED>
+__device__ __forceinline__ void edge_char(const DevMesh& m, const double* sP, int base, double* sF,
+                                          int e) {
+  constexpr int NV = D + 2;
+  const double eps4 = 4.0 * m.eps;
+  const double* col = sP + base;  // variable v of window node k at col[v NEXT + k STEP]
+  // eigensystem at the mean state: u, c, 1/c, H = (E + p) / rho,
+  // b1 = (gamma - 1) / c^2, b2 = b1 u.u / 2
+  double ub[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    ub[v] = 0.5 * (col[v * NEXT + 2 * STEP] + col[v * NEXT + 3 * STEP]);
+  const double ir = rcp_nr(ub[0]);
+  double u[D];
+  double q2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    u[i] = ub[1 + i] * ir;
+    q2 = (i == 0) ? u[0] * u[0] : fma(u[i], u[i], q2);
+  }
+  const double pb = m.gm1 * fma(-0.5 * ub[0], q2, ub[D + 1]);
+  double c, ic;
+  sqrt_rsqrt_nr(m.gamma * pb * ir, c, ic);
+  const double H = (ub[D + 1] + pb) * ir;
+  const double b1 = m.gm1 * (ic * ic);
+  const double b2 = 0.5 * b1 * q2;
+  // per node, s = b1 (E - u.m) + b2 rho and a = (u_J rho - m_J) / c: the
+  // acoustic fields are (s + a) / 2 (u_J - c) and (s - a) / 2 (u_J + c), the
+  // entropy field rho - s; the shear field of a tangential t is m_t - u_t rho
+  double sv[6], av[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double* nk = col + k * STEP;
+    double um = u[0] * nk[NEXT];
+#pragma unroll
+    for (int i = 1; i < D; ++i) um = fma(u[i], nk[(1 + i) * NEXT], um);
+    sv[k] = fma(b1, nk[(D + 1) * NEXT] - um, b2 * nk[0]);
+    av[k] = fma(u[J], nk[0], -nk[(1 + J) * NEXT]) * ic;
+  }
+  double wl[NV], wr[NV];
+  weno5_pair(0.5 * (sv[0] + av[0]), 0.5 * (sv[1] + av[1]), 0.5 * (sv[2] + av[2]),
+             0.5 * (sv[3] + av[3]), 0.5 * (sv[4] + av[4]), 0.5 * (sv[5] + av[5]), eps4, wl[0],
+             wr[0]);
+  weno5_pair(0.5 * (sv[0] - av[0]), 0.5 * (sv[1] - av[1]), 0.5 * (sv[2] - av[2]),
+             0.5 * (sv[3] - av[3]), 0.5 * (sv[4] - av[4]), 0.5 * (sv[5] - av[5]), eps4,
+             wl[NV - 1], wr[NV - 1]);
+  weno5_pair(col[0] - sv[0], col[STEP] - sv[1], col[2 * STEP] - sv[2], col[3 * STEP] - sv[3],
+             col[4 * STEP] - sv[4], col[5 * STEP] - sv[5], eps4, wl[1], wr[1]);
+  int f = 2;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    if (t == J) continue;
+    const double* mt = col + (1 + t) * NEXT;
+    weno5_pair(fma(-u[t], col[0], mt[0]), fma(-u[t], col[STEP], mt[STEP]),
+               fma(-u[t], col[2 * STEP], mt[2 * STEP]), fma(-u[t], col[3 * STEP], mt[3 * STEP]),
+               fma(-u[t], col[4 * STEP], mt[4 * STEP]), fma(-u[t], col[5 * STEP], mt[5 * STEP]),
+               eps4, wl[f], wr[f]);
+    ++f;
+  }
+  // back to conserved states: rho = W- + We + W+, m_J = u_J rho + c (W+ - W-),
+  // m_t = u_t rho + W_t, E = H (W- + W+) + u_J c (W+ - W-) + q2/2 We + sum_t u_t W_t
+  double UX[2][NV];
+  bool ok = true;
+#pragma unroll
+  for (int X = 0; X < 2; ++X) {
+    const double* w = X == 0 ? wl : wr;
+    double* U = UX[X];
+    const double A = w[0] + w[NV - 1];
+    const double B = w[NV - 1] - w[0];
+    const double rho = A + w[1];
+    double Et = 0.5 * q2 * w[1];
+    int g = 2;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      if (t == J) {
+        U[1 + t] = fma(u[J], rho, c * B);
+      } else {
+        U[1 + t] = fma(u[t], rho, w[g]);
+        Et = fma(u[t], w[g], Et);
+        ++g;
+      }
+    }
+    U[0] = rho;
+    U[D + 1] = fma(H, A, fma(u[J] * c, B, Et));
+    const double irx = rcp_nr(rho);
+    double ke = U[1] * (U[1] * irx);
+#pragma unroll
+    for (int i = 1; i < D; ++i) ke = fma(U[1 + i], U[1 + i] * irx, ke);
+    const double px = m.gm1 * fma(-0.5, ke, U[D + 1]);
+    ok = ok && (rho > 0.0) && (px > 0.0);
+  }
+  if (!ok) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      UX[0][v] = col[v * NEXT + 2 * STEP];
+      UX[1][v] = col[v * NEXT + 3 * STEP];
+    }
+  }
+  double FL[NV], FR[NV], sl, sr;
+  conserved_flux<D, J>(m, UX[0], FL, sl);
+  conserved_flux<D, J>(m, UX[1], FR, sr);
+  const double S = fmax(sr, sl);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sF[v * NED + e] = fma(-S, UX[1][v] - UX[0][v], FR[v] + FL[v]);
+}
+
+// The scheme branch taken once per edge, so that each path is straight-line
+// code the compiler can schedule across the primitives.  The characteristic
+// scheme is a separate kernel instantiation (its LDS holds conserved states).
+template <int D, int J, int NEXT, int STEP, int NED, bool CHAR>
 __device__ __forceinline__ void edge_at(const DevMesh& m, const double* sP, int base, double* sF,
                                         int e) {
-  if (m.scheme == AMR_SCHEME_CENTRAL)
+  if constexpr (CHAR)
+    edge_char<D, J, NEXT, STEP, NED>(m, sP, base, sF, e);
+  else if (m.scheme == AMR_SCHEME_CENTRAL)
     edge_at_scheme<D, J, NEXT, STEP, NED, true>(m, sP, base, sF, e);
   else
     edge_at_scheme<D, J, NEXT, STEP, NED, false>(m, sP, base, sF, e);
 }
+
 
 // Face fluxes G of direction J (flux form of Eq. (9)) from the edge fluxes
 // in sF, their divergence into acc, and the patch-boundary faces into the
 // flux registers.
 template <int D, int TX, int TY, int TZ, int NT, int J>
 __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ frp, int n,
-                                         const int o[3], double acc[][D + 2], double inv_h) {
+                                         const int o[3], double acc[][D + 2], double inv_h,
+                                         int wmask) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int G0 = S::T0 + (J == 0 ? 3 : 0);
@@ -361,6 +549,8 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
   const int nface = (D == 1) ? 1 : (D == 2 ? n : n * n);
   constexpr double c24 = 1.0 / 24.0;
   const double half_inv_h = 0.5 * inv_h;
+  // patch-boundary faces whose flux registers refluxing reads
+  const bool lo_reg = (wmask >> (2 * J)) & 1, hi_reg = (wmask >> (2 * J + 1)) & 1;
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int cell = tid + cc * NT;
@@ -393,23 +583,20 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
       const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
       const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
       acc[cc][v] = fma(-(Gp - Gm), half_inv_h, acc[cc][v]);
-      if (i == 0) frp[((J * 2 + 0) * NV + v) * nface + tang] = 0.5 * Gm;
-      if (i == n - 1) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
+      if (i == 0 && lo_reg) frp[((J * 2 + 0) * NV + v) * nface + tang] = 0.5 * Gm;
+      if (i == n - 1 && hi_reg) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
     }
   }
 }
 
-template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool UNION>
-__device__ __forceinline__ void stage_direction(const DevMesh& m, const double* __restrict__ Uin,
-                                                const double* __restrict__ Pin,
-                                                double* __restrict__ frp, int n, int full,
-                                                const int o[3], const int pc[3], int l,
-                                                const int* sN, double* sP, double* sF,
-                                                double acc[][D + 2], double inv_h) {
+// Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J, of direction J
+// from the node values in sP (the union layout in 1D/2D, the tile extended
+// along J in 3D), into sF.
+template <int D, int TX, int TY, int TZ, int NT, int J, bool UNION, bool CHAR>
+__device__ __forceinline__ void edges_dir(const DevMesh& m, const double* sP, double* sF) {
   using S = TileShape<D, TX, TY, TZ>;
-  constexpr int NV = D + 2;
-  constexpr int NQ = D + 2;
-  constexpr int E0 = UNION ? S::T0 + 8 : S::T0 + (J == 0 ? 8 : 0);
+  // E0 is the row pitch of the node array
+  constexpr int E0 = UNION ? S::UPITCH : S::xpitch(J);
   constexpr int E1 = UNION ? (D >= 2 ? S::T1 + 8 : 1) : S::T1 + (J == 1 ? 8 : 0);
   constexpr int E2 = UNION ? 1 : S::T2 + (J == 2 ? 8 : 0);
   constexpr int NEXT = E0 * E1 * E2;
@@ -418,28 +605,7 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
   constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
   constexpr int NED = G0 * G1 * G2;
   constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
-  const int tid = threadIdx.x;
-
-  // 1. primitives of the tile extended by 4 nodes on both sides along J
-  // (the union layout is loaded once by the caller for all directions)
-  if constexpr (!UNION) {
-    for (int idx = tid; idx < NEXT; idx += NT) {
-      const int e0 = idx % E0;
-      const int e1 = (idx / E0) % E1;
-      const int e2 = idx / (E0 * E1);
-      const int c[3] = {o[0] + e0 - (J == 0 ? 4 : 0), o[1] + e1 - (J == 1 ? 4 : 0),
-                        o[2] + e2 - (J == 2 ? 4 : 0)};
-      double u[NV], q[NQ];
-      node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u);
-      node_primitives<D>(m, u, q);
-#pragma unroll
-      for (int k = 0; k < NQ; ++k) sP[k * NEXT + idx] = q[k];
-    }
-    __syncthreads();
-  }
-
-  // 2. Riemann flux at every edge i+1/2, i = o_J-2 .. o_J+T_J
-  for (int e = tid; e < NED; e += NT) {
+  for (int e = threadIdx.x; e < NED; e += NT) {
     const int a0 = e % G0;
     const int a1 = (e / G0) % G1;
     const int a2 = e / (G0 * G1);
@@ -448,45 +614,107 @@ __device__ __forceinline__ void stage_direction(const DevMesh& m, const double* 
     if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);
     else if constexpr (J == 0) base = (D >= 2 ? (a1 + 4) * E0 : 0) + a0;
     else base = a1 * E0 + (a0 + 4);
-    edge_at<D, J, NEXT, STEP, NED>(m, sP, base, sF, e);
+    edge_at<D, J, NEXT, STEP, NED, CHAR>(m, sP, base, sF, e);
   }
-  __syncthreads();
+}
 
-  // 3. face fluxes G and their divergence
-  cells_at<D, TX, TY, TZ, NT, J>(sF, frp, n, o, acc, inv_h);
+// 3D: primitives (conserved values for the characteristic scheme) of the
+// tile extended by 4 nodes on both sides along J, into sP in the
+// extended-box layout.  The tile's own nodes come first in the thread order
+// and the 8 halo layers after them, so that a wave holds nodes of one kind
+// (the tile's own nodes are read straight from the patch); every thread
+// issues the loads of all its nodes before converting any.
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool CHAR>
+__device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restrict__ Uin,
+                                         const double* __restrict__ Pin, int n, int full,
+                                         const int o[3], const int pc[3], int l,
+                                         const long long* sN, double* sP) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int E0 = S::xpitch(J);             // row pitch
+  constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
+  constexpr int E2 = S::T2 + (J == 2 ? 8 : 0);
+  constexpr int NEXT = E0 * E1 * E2;
+  constexpr int NC = S::NCELL;
+  constexpr int TJ = J == 0 ? S::T0 : (J == 1 ? S::T1 : S::T2);
+  constexpr int HL = NC / TJ;                  // nodes of one layer across J
+  constexpr int CA = J == 0 ? S::T1 : S::T0;   // extent of the lower cross direction
+  constexpr int NNODE = NC + 8 * HL;           // nodes of the extended box
+  constexpr int ITER = (NNODE + NT - 1) / NT;
+  double u[ITER][NV];
+  int lidx[ITER];
+#pragma unroll
+  for (int k = 0; k < ITER; ++k) {
+    const int idx = threadIdx.x + k * NT;
+    lidx[k] = -1;
+    if (idx >= NNODE) continue;
+    int t[3];
+    if (idx < NC) {
+      t[0] = idx % S::T0;
+      t[1] = (idx / S::T0) % S::T1;
+      t[2] = idx / (S::T0 * S::T1);
+    } else {
+      const int hh = idx - NC;
+      const int layer = hh / HL;                // -4..-1, then T_J..T_J+3
+      const int r = hh - layer * HL;
+      const int a = r % CA, b = r / CA;         // the two other directions, lower first
+      t[J] = layer < 4 ? layer - 4 : TJ + layer - 4;
+      t[J == 0 ? 1 : 0] = a;
+      t[J == 2 ? 1 : 2] = b;
+    }
+    const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
+    lidx[k] = (t[0] + (J == 0 ? 4 : 0)) + E0 * ((t[1] + (J == 1 ? 4 : 0)) +
+                                                E1 * (t[2] + (J == 2 ? 4 : 0)));
+    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < ITER; ++k)
+    if (lidx[k] >= 0) node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
+}
+
+// 1D/2D: edge fluxes and their divergence for direction J from the union
+// layout loaded once for all directions.
+template <int D, int TX, int TY, int TZ, int NT, int J, bool CHAR>
+__device__ __forceinline__ void stage_direction(const DevMesh& m, double* __restrict__ frp, int n,
+                                                const int o[3], double* sP, double* sF,
+                                                double acc[][D + 2], double inv_h, int wmask) {
+  edges_dir<D, TX, TY, TZ, NT, J, true, CHAR>(m, sP, sF);
+  __syncthreads();
+  cells_at<D, TX, TY, TZ, NT, J>(sF, frp, n, o, acc, inv_h, wmask);
   __syncthreads();
 }
 
 // 2D union layout, both directions at once: the x and y edges form one work
 // range (x first), then every cell takes its x and then its y divergence,
 // the order of the direction-by-direction path.
-template <int D, int TX, int TY, int NT>
+template <int D, int TX, int TY, int NT, bool CHAR>
 __device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict__ frp, int n,
                                            const int o[3], const double* sP, double* sFx,
-                                           double* sFy, double acc[][D + 2], double inv_h) {
+                                           double* sFy, double acc[][D + 2], double inv_h,
+                                           int wmask) {
   static_assert(D == 2, "combined sweep is 2D");
   using S = TileShape<D, TX, TY, 1>;
-  constexpr int E0 = S::T0 + 8, E1 = S::T1 + 8;
-  constexpr int NEXT = E0 * E1;
+  constexpr int E0 = S::UPITCH;                // row pitch of the union box
+  constexpr int NEXT = S::NUNION;
   constexpr int GX0 = S::T0 + 3, NEDX = GX0 * S::T1;
   constexpr int GY0 = S::T0, NEDY = S::T0 * (S::T1 + 3);
   for (int e = threadIdx.x; e < NEDX + NEDY; e += NT) {
     if (e < NEDX) {
       const int a0 = e % GX0, a1 = e / GX0;
-      edge_at<D, 0, NEXT, 1, NEDX>(m, sP, (a1 + 4) * E0 + a0, sFx, e);
+      edge_at<D, 0, NEXT, 1, NEDX, CHAR>(m, sP, (a1 + 4) * E0 + a0, sFx, e);
     } else {
       const int f = e - NEDX;
       const int a0 = f % GY0, a1 = f / GY0;
-      edge_at<D, 1, NEXT, E0, NEDY>(m, sP, a1 * E0 + (a0 + 4), sFy, f);
+      edge_at<D, 1, NEXT, E0, NEDY, CHAR>(m, sP, a1 * E0 + (a0 + 4), sFy, f);
     }
   }
   __syncthreads();
-  cells_at<D, TX, TY, 1, NT, 0>(sFx, frp, n, o, acc, inv_h);
-  cells_at<D, TX, TY, 1, NT, 1>(sFy, frp, n, o, acc, inv_h);
+  cells_at<D, TX, TY, 1, NT, 0>(sFx, frp, n, o, acc, inv_h, wmask);
+  cells_at<D, TX, TY, 1, NT, 1>(sFy, frp, n, o, acc, inv_h, wmask);
 }
 
-template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 : 7))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH, bool CHAR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (D <= 2 ? 6 : 7)))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
                                               const int* __restrict__ tiles, int count,
@@ -499,7 +727,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 :
   constexpr int NV = D + 2;
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
   constexpr bool UNION = D <= 2;
-  constexpr int NU = (S::T0 + 8) * (D >= 2 ? S::T1 + 8 : 1);
+  constexpr int NU = S::NUNION;
   // edge fluxes: one direction at a time, or x and y together (BOTH)
   constexpr int NEDXY = (S::T0 + 3) * S::T1 + S::T0 * (S::T1 + 3);
   __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
@@ -516,6 +744,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 :
   const long long base = patch_base(m, pid, l);
   const double* Pin = Uin + base;
   double* frp = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
+  // faces whose flux registers are written (the second half of the mask array)
+  const int wmask = cfmask[m.max_patches + pid];
   double acc[CPT][NV];
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc)
@@ -523,27 +753,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D <= 2 ? 6 :
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
-  __shared__ int sN[27];
+  __shared__ long long sN[27];
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
   }
   if constexpr (UNION) {
-    load_union<D, TX, TY, NT, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    load_union<D, TX, TY, NT, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
     __syncthreads();
-  }
-  if constexpr (BOTH && D == 2) {
-    stage_both<D, TX, TY, NT>(m, frp, n, o, sP, sF, sF + (D + 2) * ((S::T0 + 3) * S::T1), acc,
-                              L.inv_h);
+    if constexpr (BOTH && D == 2) {
+      stage_both<D, TX, TY, NT, CHAR>(m, frp, n, o, sP, sF,
+                                      sF + (D + 2) * ((S::T0 + 3) * S::T1), acc, L.inv_h, wmask);
+    } else {
+      stage_direction<D, TX, TY, TZ, NT, 0, CHAR>(m, frp, n, o, sP, sF, acc, L.inv_h, wmask);
+      if constexpr (D >= 2)
+        stage_direction<D, TX, TY, TZ, NT, 1, CHAR>(m, frp, n, o, sP, sF, acc, L.inv_h, wmask);
+    }
   } else {
-    stage_direction<D, TX, TY, TZ, NT, 0, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
-                                                       sP, sF, acc, L.inv_h);
-    if constexpr (D >= 2)
-      stage_direction<D, TX, TY, TZ, NT, 1, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
-                                                         sP, sF, acc, L.inv_h);
-    if constexpr (D >= 3)
-      stage_direction<D, TX, TY, TZ, NT, 2, FUSE, UNION>(m, Uin, Pin, frp, n, full, o, pc, l, sN,
-                                                         sP, sF, acc, L.inv_h);
+    // 3D, direction by direction: the next direction's nodes are loaded in
+    // the phase that forms the previous direction's divergence (sP is free
+    // once the edges are done, sF is read), two block barriers per direction
+    load_dir<D, TX, TY, TZ, NT, 0, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    __syncthreads();
+    edges_dir<D, TX, TY, TZ, NT, 0, false, CHAR>(m, sP, sF);
+    __syncthreads();
+    load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
+    __syncthreads();
+    edges_dir<D, TX, TY, TZ, NT, 1, false, CHAR>(m, sP, sF);
+    __syncthreads();
+    load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
+    __syncthreads();
+    edges_dir<D, TX, TY, TZ, NT, 2, false, CHAR>(m, sP, sF);
+    __syncthreads();
+    cells_at<D, TX, TY, TZ, NT, 2>(sF, frp, n, o, acc, L.inv_h, wmask);
   }
 
   const long long vs = var_stride<D>(full);
@@ -654,16 +898,24 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
   // one block per work item, rounded up to whole groups of kXcds blocks (see
   // xcd_item)
   const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
-#define AMR_STAGE_F(D, TX, TY, TZ, NT, F, B)                                                \
-  do {                                                                                       \
-    if (ev0)                                                                                 \
-      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, ev0, \
-                            ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next,   \
-                            cfmask, lam_in, dt_out);                                         \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B>), dim3(nb), dim3(NT), 0, s, m,     \
-                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask, lam_in, \
-                         dt_out);                                                            \
+  const bool chr = m.scheme == AMR_SCHEME_CHAR;
+#define AMR_STAGE_K(D, TX, TY, TZ, NT, F, B, C)                                                \
+  do {                                                                                          \
+    if (ev0)                                                                                    \
+      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B, C>), dim3(nb), dim3(NT), 0, s,     \
+                            ev0, ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next, \
+                            cfmask, lam_in, dt_out);                                            \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B, C>), dim3(nb), dim3(NT), 0, s, m,     \
+                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask, lam_in,    \
+                         dt_out);                                                               \
+  } while (0)
+#define AMR_STAGE_F(D, TX, TY, TZ, NT, F, B)          \
+  do {                                                \
+    if (chr)                                          \
+      AMR_STAGE_K(D, TX, TY, TZ, NT, F, B, true);     \
+    else                                              \
+      AMR_STAGE_K(D, TX, TY, TZ, NT, F, B, false);    \
   } while (0)
 #define AMR_STAGE(D, TX, TY, TZ, NT, B)        \
   do {                                         \
@@ -687,6 +939,7 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
   }
 #undef AMR_STAGE
 #undef AMR_STAGE_F
+#undef AMR_STAGE_K
 }
 
 }  // namespace amr

@@ -241,29 +241,51 @@ def learned_regrid(h: A.Hierarchy, pred: A.Predictor, tau: float, rounds: int = 
     return changed
 
 
+def cover(h: A.Hierarchy, max_rounds: int) -> int:
+    """The judge's fallback: plain regrids until the plain tagger finds no
+    tagged cell outside the finest leaves (each regrid can add one level), at
+    most ``max_rounds``; returns the regrids made, or -1 when the mesh still
+    misses tags after them."""
+    made = 0
+    while h.judge():
+        if made == max_rounds:
+            return -1
+        h.adapt()
+        made += 1
+    return made
+
+
 def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                pred: Optional[A.Predictor] = None, tau: float = 0.5,
-               judge: bool = False, rounds: int = 1) -> RunStats:
+               judge: bool = False, rounds: int = 1, regrid_buffer: Optional[int] = None) -> RunStats:
     """Advance `steps` steps under a regrid policy; wall time includes
-    tagging, prediction, judging and regridding."""
+    tagging, prediction, judging and regridding.
+
+    Every `every` steps the policy regrids (plain tags, or the predicted and
+    plain requests together), with the tag dilation `regrid_buffer` when
+    given (the hierarchy's own otherwise).  With the judge on, after every
+    step (and its scheduled regrid) the plain tagger at the hierarchy's own
+    dilation checks that the mesh the next step runs on covers every tagged
+    cell; when it does not, plain regrids follow until it does (at most
+    max_levels - 1, the fallback).  A step whose mesh still misses tags after
+    that counts as uncovered, so coverage is the fraction of steps that ran
+    on a mesh covering the plain tags."""
     torch = A._torch()
     dt = torch.zeros(1, dtype=torch.float64, device=h.device)
     tsim = torch.zeros(1, dtype=torch.float64, device=h.device)
     regrids = fallbacks = uncovered = cells = 0
+    own_buffer = h.cfg.tag_buffer
+    max_rounds = h.cfg.max_levels - 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(1, steps + 1):
         cells += h.leaf_cells()
         h.step(dt)
         tsim += dt
-        if judge:
-            unc = h.judge()
-            if unc:
-                uncovered += 1
-                h.adapt()
-                fallbacks += 1
         if every > 0 and s % every == 0:
             regrids += 1
+            if regrid_buffer is not None:
+                h.set_tag_buffer(regrid_buffer)
             if policy == "plain":
                 h.adapt()
             else:
@@ -276,6 +298,14 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                         raise
                     h.adapt()
                     fallbacks += 1
+            if regrid_buffer is not None:
+                h.set_tag_buffer(own_buffer)
+        if judge and s < steps:
+            made = cover(h, max_rounds)
+            if made != 0:
+                fallbacks += 1
+            if made < 0:
+                uncovered += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells)

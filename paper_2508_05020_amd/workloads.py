@@ -132,6 +132,42 @@ CONFIGS = {
 }
 
 
+def blast_refinements(cfg: AMRConfig, seed: int):
+    """Refinements that build a mesh of every level of ``cfg`` around the
+    first blast centre of ``seed`` (3D, at least 3 levels): the root
+    holding the centre, then the level-1 patch of that root nearest the
+    centre whose Moore neighbours lie in the same root (local index 1 .. m-2
+    of m), then its child on the root's inner side, and so on, so that the
+    neighbours the refinement rules add stay inside the root.  Returns one
+    list of (level, coord) keys per refinement round."""
+    c = _blast_sources(np.random.default_rng(seed), cfg.dim, cfg.lo, cfg.hi - cfg.lo)[0][0]
+    span = cfg.hi - cfg.lo
+    n = cfg.patch_cells
+    root = tuple(int((c[j] - cfg.lo) / span * cfg.cells(0)) // n[0] for j in range(cfg.dim))
+    per = 2 * n[0] // n[1]
+    q = []
+    for j in range(cfg.dim):
+        g = int((c[j] - cfg.lo) / span * cfg.cells(1)) // n[1] - root[j] * per
+        q.append(root[j] * per + min(max(g, 1), per - 2))
+    rounds = [[(0, root)], [(1, tuple(q))]]
+    inner = [q[j] - root[j] * per == 1 for j in range(cfg.dim)]
+    for level in range(2, cfg.max_levels - 1):
+        r = 2 * n[level - 1] // n[level]
+        q = [r * q[j] + ((r - 1) if inner[j] else 0) for j in range(cfg.dim)]
+        rounds.append([(level, tuple(q))])
+    return rounds
+
+
+def c5_sample_config() -> AMRConfig:
+    """The 3D benchmark layout (patches 32/16/16/8 on 4 levels, blasts plus
+    the k^-2 density field) on a 64^3 base; with ``blast_refinements`` it is
+    a mesh of about 750 k leaf cells with coarse/fine faces on every level."""
+    return AMRConfig(name="c5-sample", dim=3, base_cells=64, patch_cells=[32, 16, 16, 8],
+                     periodic=[True] * 3, ic="blasts_perturbed", tag_buffer=2,
+                     regrid_interval=8, max_patches=8 + 512 + 1024 + 8192,
+                     level_capacity=(8, 512, 1024, 8192))
+
+
 def config(name: str, **overrides) -> AMRConfig:
     c = CONFIGS[name].replace(**overrides) if overrides else CONFIGS[name]
     c.validate()
@@ -161,6 +197,24 @@ def patch_points(cfg: AMRConfig, level: int, coord: Sequence[int],
     # meshgrid in (z, y, x) order so that x is the last axis
     grids = np.meshgrid(*reversed(axes), indexing="ij")
     return list(reversed(grids))
+
+
+def patch_points_batch(cfg: AMRConfig, level: int, coords) -> List[np.ndarray]:
+    """Sample points of the interior cells of several patches of one level:
+    ``[x, y, z][:dim]``, each of shape ``(P,) + (n,)*dim`` (patch first, then
+    the array axis order of ``patch_points``)."""
+    n = cfg.patch_cells[level]
+    h = cfg.h(level)
+    d = cfg.dim
+    c = np.asarray(coords, dtype=np.int64).reshape(len(coords), d)
+    out = []
+    for j in range(d):
+        g = c[:, j][:, None] * n + np.arange(n)[None, :]         # [P, n]
+        v = cfg.lo + (g + 0.5) * h
+        shp = [len(coords)] + [1] * d
+        shp[d - j] = n
+        out.append(np.broadcast_to(v.reshape(shp), (len(coords),) + (n,) * d))
+    return out
 
 
 def _min_image(dx: np.ndarray, length: float) -> np.ndarray:
@@ -273,6 +327,43 @@ def _blast_pressure(src, pts, dim: int, L: float) -> np.ndarray:
     return p
 
 
+def _grid_axes(pts, dim: int):
+    """Per-patch axis coordinates [P, m] when pts are P tensor grids stacked
+    along a leading axis (as patch_points_batch makes them), else None."""
+    if pts[0].ndim != dim + 1:
+        return None
+    vals = []
+    for j in range(dim):
+        ax = dim - j                      # array axis of x_j after the patch axis
+        idx = [slice(None)] + [0] * dim
+        idx[ax] = slice(None)
+        v = pts[j][tuple(idx)]            # [P, m]
+        shp = [v.shape[0]] + [1] * dim
+        shp[ax] = v.shape[1]
+        if not np.array_equal(np.broadcast_to(v.reshape(shp), pts[j].shape), pts[j]):
+            return None
+        vals.append(v)
+    return vals
+
+
+def _blast_pressure_grids(src, axes, dim: int, L: float) -> np.ndarray:
+    """_blast_pressure on stacked tensor grids: the per-axis squared
+    distances are formed once per axis and broadcast, summed in the same
+    order (x, then y, then z), so every point gets the same value."""
+    P, m = axes[0].shape
+    full = (P,) + (m,) * dim
+    p = np.ones(full)
+    for c, pj, rad in src:
+        r2 = np.zeros(full)
+        for j in range(dim):
+            dj = _min_image(axes[j] - c[j], L)
+            shp = [P] + [1] * dim
+            shp[dim - j] = m
+            r2 = r2 + (dj * dj).reshape(shp)
+        p = np.where(r2 < rad * rad, np.maximum(p, pj), p)
+    return p
+
+
 def blasts(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0) -> Prim:
     """rho = 1, u = 0, p = 1 except inside 6 spheres where p = p_jump (ratio reading)."""
     rng = np.random.default_rng(seed)
@@ -280,7 +371,9 @@ def blasts(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0) -> Prim:
     src = _blast_sources(rng, dim, lo, L)
 
     def f(pts):
-        p = _blast_pressure(src, pts, dim, L)
+        axes = _grid_axes(pts, dim)
+        p = (_blast_pressure_grids(src, axes, dim, L) if axes is not None
+             else _blast_pressure(src, pts, dim, L))
         return (np.ones_like(p), [np.zeros_like(p) for _ in range(dim)], p)
     return f
 
@@ -341,6 +434,22 @@ def blasts_perturbed(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0,
     def perturbation(pts):
         # sum_k c_k prod_j exp(i 2 pi k_j (x_j - lo) / L), contracted one axis
         # at a time (x, then y, then z); the real part is the cosine sum
+        gb = _grid_axes(pts, dim)
+        if gb is not None:
+            P, m = gb[0].shape
+            e = [np.exp((2j * np.pi / L) * (ks[None, :, None] * (gb[j][:, None, :] - lo)))
+                 for j in range(dim)]                                    # [P, k_j, m]
+            # contract k_x, then k_y, then k_z, as on a single patch
+            t = np.matmul(coef.reshape(-1, K)[None], e[0])              # [P, (k_z, k_y), x]
+            if dim == 1:
+                return t.reshape(P, m).real
+            t = t.reshape((P,) + (K,) * (dim - 1) + (m,))
+            t = np.matmul(np.swapaxes(t, -1, -2), e[1][:, None] if dim == 3 else e[1])
+            if dim == 2:                                                 # [P, x, y]
+                return np.swapaxes(t, 1, 2).real
+            # t: [P, k_z, x, y] -> [P, x, y, k_z] @ [P, k_z, z] -> [P, x, y, z]
+            t = np.matmul(t.transpose(0, 2, 3, 1).reshape(P, m * m, K), e[2])
+            return t.reshape(P, m, m, m).transpose(0, 3, 2, 1).real
         g = axis_values(pts)
         if g is not None:
             e = [np.exp((2j * np.pi / L) * np.outer(ks, g[j] - lo)) for j in range(dim)]
@@ -363,7 +472,9 @@ def blasts_perturbed(seed: int, dim: int = 3, lo: float = 0.0, hi: float = 1.0,
         return out.reshape(shape)
 
     def f(pts):
-        p = _blast_pressure(src, pts, dim, L)
+        axes = _grid_axes(pts, dim)
+        p = (_blast_pressure_grids(src, axes, dim, L) if axes is not None
+             else _blast_pressure(src, pts, dim, L))
         return (1.0 + perturbation(pts), [np.zeros_like(p) for _ in range(dim)], p)
     return f
 

@@ -6,6 +6,9 @@ nothing computed by the library is fed to the oracle except, in lockstep runs,
 the regrid requests (reported and compared, see the lockstep test)."""
 from __future__ import annotations
 
+import copy
+import functools
+
 import numpy as np
 
 from paper_2508_05020_amd import workloads as W
@@ -13,6 +16,9 @@ from oracle.solver import OracleAMR
 
 # Parity bar: relative L-infinity per conserved variable, max over variables.
 TOL = 1e-12
+
+# oracle scheme name -> the library's amr_config.scheme value
+SCHEMES = {"weno": 0, "central": 1, "char": 2}
 
 
 def case_config(name: str):
@@ -46,6 +52,13 @@ def case_config(name: str):
                           periodic=[True] * 3, ic="blasts", max_patches=4096)
         picks = [[(0, (1, 1, 1))], [(1, (3, 3, 3))]]
         return cfg, W.blasts(3001, 3), picks
+    if name == "3d-c5":
+        # the layout and generator of the 3D benchmark workload (patches
+        # 32/16/16/8 on 4 levels, blast waves plus the k^-2 density field) on
+        # a 64^3 base; one root refined around the first blast and one patch
+        # per finer level, so that every level has coarse/fine faces
+        cfg = W.c5_sample_config()
+        return cfg, W.blasts_perturbed(5001, 3), W.blast_refinements(cfg, 5001)
     if name == "3d-uneven":
         cfg = W.AMRConfig(name="p3u", dim=3, base_cells=32, patch_cells=[16, 8],
                           periodic=[True, False, True], ic="blasts", max_patches=4096)
@@ -55,6 +68,13 @@ def case_config(name: str):
 
 
 def oracle_for(name: str):
+    """A fresh copy of the named case's oracle hierarchy (built once)."""
+    o, gen = _oracle_for(name)
+    return copy.deepcopy(o), gen
+
+
+@functools.lru_cache(maxsize=4)
+def _oracle_for(name: str):
     cfg, gen, picks = case_config(name)
     o = OracleAMR(cfg)
     if picks is None:
@@ -110,6 +130,26 @@ def tensor_patches(h, flat, pid_of):
         off = h.offset(p)
         out[k] = host[off:off + size].reshape((h.nvar,) + (n,) * h.cfg.dim)
     return out
+
+
+def rhs_error(got: dict, ref: dict, U: dict, keys, d, dt: float):
+    """Parity metric of L(U), per conserved variable v: max|L_gpu - L_ref|
+    over the compared cells divided by the larger of max|L_ref,v| and
+    max|U_v| / dt (dt the step's CFL time step), maximum over variables.
+    The second scale is the state change a stage makes per unit L: where a
+    variable's L is a small difference of large flux terms (the density of
+    a gas at rest with uniform density, whose L comes only from
+    interpolation differences), its rounding is bounded by the stage update
+    it causes rather than by its own near-zero size."""
+    nv = d + 2
+    num = np.zeros(nv)
+    den = np.zeros(nv)
+    for k in keys:
+        g, r, u = got[k], ref[k], interior(U[k], d)
+        for v in range(nv):
+            num[v] = max(num[v], float(np.max(np.abs(g[v] - r[v]))))
+            den[v] = max(den[v], float(np.max(np.abs(r[v]))), float(np.max(np.abs(u[v]))) / dt)
+    return float(np.max(num / np.where(den > 0, den, 1.0)))
 
 
 def interior(a, d, ng=4):

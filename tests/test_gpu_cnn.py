@@ -131,9 +131,14 @@ def test_gradients_match_reference(amr):
     assert loss.item() == pytest.approx(rl, rel=2e-2)
     ref = _flat(rg)
     offs = [0, 576, 592, 2896, 2912, 3056, 3057]
+    # per parameter block: element-wise, max |g - ref| against the block's
+    # largest reference gradient, and the L2 relative error
     for a, b in zip(offs[:-1], offs[1:]):
-        err = np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-12)
-        assert err <= 2e-2, (a, b, err)
+        scale = max(float(np.max(np.abs(ref[a:b]))), 1e-12)
+        elem = float(np.max(np.abs(g[a:b] - ref[a:b]))) / scale
+        l2 = np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-12)
+        print(f"block [{a}, {b}): element-wise {elem:.3e}, L2 {l2:.3e}")
+        assert elem <= 2e-2 and l2 <= 2e-2, (a, b, elem, l2)
 
 
 def test_adam_step_matches_reference(amr):

@@ -18,7 +18,13 @@ from tests import _harness as H
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["1d", "2d", "2d-wall", "2d-32", "implosion", "3d", "3d-uneven"]
+CASES = ["1d", "2d", "2d-wall", "2d-32", "implosion", "3d", "3d-uneven", "3d-c5"]
+# the interpolation variants of Section 2.2: WENO5-JS of the primitives on
+# every case; the central interpolation of Eq. (8) and WENO5-JS of the
+# characteristic variables on the 1D, 2D and smaller 3D cases
+SCHEME_CASES = [(n, "weno") for n in CASES] + \
+    [(n, "central") for n in ("1d", "2d", "2d-32", "implosion", "3d", "3d-uneven")] + \
+    [(n, "char") for n in ("1d", "2d", "2d-wall", "2d-32", "implosion", "3d", "3d-uneven")]
 
 
 @pytest.fixture(scope="module")
@@ -27,9 +33,11 @@ def amr():
     return A
 
 
-def _pair(name, amr, exec_mode=None):
+def _pair(name, amr, exec_mode=None, scheme="weno"):
     o, gen = H.oracle_for(name)
-    h = amr.Hierarchy(o.cfg, exec_mode=amr.EXEC_BATCHED if exec_mode is None else exec_mode)
+    o.scheme = scheme
+    h = amr.Hierarchy(o.cfg, exec_mode=amr.EXEC_BATCHED if exec_mode is None else exec_mode,
+                      scheme=H.SCHEMES[scheme])
     pid_of, key_of = H.mirror(o, h)
     return o, h, pid_of, key_of
 
@@ -55,16 +63,16 @@ def test_fill_ghosts_bitwise(name, amr):
         assert np.array_equal(got[k], o.U[0][k]), k
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_rhs_parity(name, amr):
-    o, h, pid_of, _ = _pair(name, amr)
+@pytest.mark.parametrize("name,scheme", SCHEME_CASES)
+def test_rhs_parity(name, scheme, amr):
+    o, h, pid_of, _ = _pair(name, amr, scheme=scheme)
     L = h.rhs(0)
     o.fill_ghosts(0, o.forest.leaves())
     ref = o.rhs(0)
     got = H.tensor_patches(h, L, pid_of)
     d = o.cfg.dim
     gint = {k: H.interior(got[k], d) for k in ref}
-    err = H.rel_linf(gint, ref, list(ref), d, region="none")
+    err = H.rhs_error(gint, ref, o.U[0], list(ref), d, o.compute_dt(0))
     assert err <= H.TOL, err
 
 
@@ -76,9 +84,9 @@ def test_dt_parity(name, amr):
     assert abs(dt - ref) <= 1e-14 * ref, (dt, ref)
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_rk_stages_parity(name, amr):
-    o, h, pid_of, _ = _pair(name, amr)
+@pytest.mark.parametrize("name,scheme", SCHEME_CASES)
+def test_rk_stages_parity(name, scheme, amr):
+    o, h, pid_of, _ = _pair(name, amr, scheme=scheme)
     d = o.cfg.dim
     dt_dev = h.compute_dt(0)
     dt = o.compute_dt(0)
@@ -138,18 +146,18 @@ def test_regrid_parity(name, amr):
         assert np.array_equal(H.interior(got[k], d), H.interior(o.U[0][k], d)), k
 
 
-@pytest.mark.parametrize("name", ["1d", "2d", "implosion", "3d-uneven"])
-def test_lockstep_steps_with_regrid(name, amr):
-    """Several steps with regrids every second step.  Both sides tag their own
-    state; the request sets must agree (no decision within round-off of the
-    threshold is expected), and the oracle's requests drive both regrids."""
-    o, h, pid_of, key_of = _pair(name, amr)
+def _lockstep(o, h, pid_of, key_of, nsteps, every, check_every_regrid=False):
+    """Advance both sides ``nsteps`` steps with a regrid every ``every``
+    steps.  Both sides tag their own state; the request sets must agree (no
+    decision within round-off of the threshold is expected), and the
+    oracle's requests drive both regrids.  Returns the number of regrids that
+    changed the mesh and the final pid map."""
     d = o.cfg.dim
-    nsteps = 6
+    changed = regrids = 0
     for s in range(1, nsteps + 1):
         h.step()
         o.step()
-        if s % 2 == 0:
+        if s % every == 0:
             refine, coarsen, _ = h.tag(0)
             o.fill_ghosts(0, o.tag_keys())
             has, _ = o.tag(0)
@@ -164,19 +172,62 @@ def test_lockstep_steps_with_regrid(name, amr):
             for k in ocoa:
                 cq[pid_of[k]] = 1
             h.regrid(rq, cq)
-            o.regrid(oref, ocoa)
+            created, deleted = o.regrid(oref, ocoa)
+            changed += bool(created or deleted)
+            regrids += 1
             pid_of = {(t["level"], t["coord"]): t["pid"] for t in h.patch_table()}
             key_of = {v: k for k, v in pid_of.items()}
             assert set(pid_of) == set(o.forest.keys())
+            if check_every_regrid:
+                got = H.download(h, 0, pid_of)
+                err = H.rel_linf(got, o.U[0], o.forest.keys(), d)
+                assert err <= H.TOL, (s, err)
     got = H.download(h, 0, pid_of)
     err = H.rel_linf(got, o.U[0], o.forest.keys(), d)
     assert err <= H.TOL, err
+    return changed, regrids
 
 
-@pytest.mark.parametrize("name", ["1d", "2d", "3d"])
-def test_batched_equals_per_patch_bitwise(name, amr):
-    o, h1, pid1, _ = _pair(name, amr, exec_mode=amr.EXEC_BATCHED)
-    o2, h2, pid2, _ = _pair(name, amr, exec_mode=amr.EXEC_PER_PATCH)
+@pytest.mark.parametrize("name", ["1d", "2d", "implosion", "3d-uneven"])
+def test_lockstep_steps_with_regrid(name, amr):
+    """Several steps with regrids every second step."""
+    o, h, pid_of, key_of = _pair(name, amr)
+    _lockstep(o, h, pid_of, key_of, 6, 2)
+
+
+def test_lockstep_c1_whole_run(amr):
+    """The 1D shock-tube workload (2 levels, patches of 16, transmissive) for
+    its whole run: 200 steps at CFL 0.5 with a regrid every 4 steps, the
+    state compared after every regrid."""
+    cfg = W.config("c1")
+    o = OracleAMR(cfg)
+    o.init_from_ic(W.initial_data(cfg, 1001))
+    h = amr.Hierarchy(cfg)
+    pid_of, key_of = H.mirror(o, h)
+    changed, regrids = _lockstep(o, h, pid_of, key_of, cfg.steps, cfg.regrid_interval,
+                                 check_every_regrid=True)
+    assert regrids == cfg.steps // cfg.regrid_interval and changed >= 1
+
+
+def test_lockstep_c2_full_size(amr):
+    """The 2D benchmark workload at full size (base 256^2, 3 levels, patches
+    32/16/16) for 20 steps with its regrid every 4 steps (5 regrids), every
+    leaf cell compared after each regrid and at the end."""
+    cfg = W.config("c2")
+    o = OracleAMR(cfg)
+    o.init_from_ic(W.initial_data(cfg, 2001))
+    h = amr.Hierarchy(cfg)
+    pid_of, key_of = H.mirror(o, h)
+    _, regrids = _lockstep(o, h, pid_of, key_of, 20, cfg.regrid_interval,
+                           check_every_regrid=True)
+    assert regrids == 5
+
+
+@pytest.mark.parametrize("name,scheme", [("1d", "weno"), ("2d", "weno"), ("3d", "weno"),
+                                         ("3d", "char")])
+def test_batched_equals_per_patch_bitwise(name, scheme, amr):
+    o, h1, pid1, _ = _pair(name, amr, exec_mode=amr.EXEC_BATCHED, scheme=scheme)
+    o2, h2, pid2, _ = _pair(name, amr, exec_mode=amr.EXEC_PER_PATCH, scheme=scheme)
     for _ in range(2):
         h1.step()
         h2.step()
@@ -194,12 +245,13 @@ def test_batched_equals_per_patch_bitwise(name, amr):
         assert np.array_equal(H.interior(a[k], d), H.interior(b[k], d)), k
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
-def test_uniform_state_bitwise_gpu(d, amr):
+@pytest.mark.parametrize("d,scheme", [(1, "weno"), (2, "weno"), (3, "weno"), (1, "char"),
+                                      (2, "char"), (3, "char")])
+def test_uniform_state_bitwise_gpu(d, scheme, amr):
     base = {1: 64, 2: 64, 3: 32}[d]
     cfg = W.AMRConfig(name="u", dim=d, base_cells=base, patch_cells=[8, 8, 8],
                       periodic=[True] * (d - 1) + [False], max_patches=8192)
-    h = amr.Hierarchy(cfg)
+    h = amr.Hierarchy(cfg, scheme=H.SCHEMES[scheme])
     gen = W.uniform_state(d, 900 + d)
     amr.init_from_ic(h, gen)
     ref = amr.patch_primitives(cfg, 0, (0,) * d, gen)
@@ -256,21 +308,6 @@ def test_conservation_gpu(amr):
     assert np.max(np.abs(t1 - t0)) / scale <= 1e-13 * 8
 
 
-def test_full_size_c2_one_step(amr):
-    """The benchmark workload (c2: 2D, 256^2 base, 3 levels) in the benchmark's
-    launch configuration: every leaf cell after one step."""
-    cfg = W.config("c2")
-    o = OracleAMR(cfg)
-    o.init_from_ic(W.initial_data(cfg, 2001))
-    h = amr.Hierarchy(cfg)
-    pid_of, _ = H.mirror(o, h, bufs=(0,))
-    h.step()
-    o.step()
-    got = H.download(h, 0, pid_of)
-    err = H.rel_linf(got, o.U[0], o.forest.keys(), 2)
-    assert err <= H.TOL, err
-
-
 def test_capacity_error_is_transactional(amr):
     cfg = W.AMRConfig(name="cap", dim=2, base_cells=64, patch_cells=[16, 16, 16],
                       periodic=[True, True], max_patches=16 + 8 + 8)
@@ -296,10 +333,11 @@ def test_nonphysical_detected(amr):
     assert h.check() >= 1
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_fused_halo_equals_explicit_fill_bitwise(name, amr):
-    o, h1, pid1, _ = _pair(name, amr)
-    _, h2, pid2, _ = _pair(name, amr)
+@pytest.mark.parametrize("name,scheme", [(n, "weno") for n in CASES] +
+                         [("2d-32", "char"), ("3d-uneven", "char")])
+def test_fused_halo_equals_explicit_fill_bitwise(name, scheme, amr):
+    o, h1, pid1, _ = _pair(name, amr, scheme=scheme)
+    _, h2, pid2, _ = _pair(name, amr, scheme=scheme)
     h2.set_fused_halo(False)
     for _ in range(2):
         h1.step()
@@ -340,8 +378,9 @@ def test_graph_replays_equal_eager_bitwise(name, amr):
             assert set(pg) == set(pe)
 
 
-@pytest.mark.parametrize("name", ["2d", "3d", "3d-uneven"])
-def test_tile_variants_bitwise_and_autotune(name, amr):
+@pytest.mark.parametrize("name,scheme", [("2d", "weno"), ("3d", "weno"), ("3d-uneven", "weno"),
+                                         ("2d", "char"), ("3d", "char")])
+def test_tile_variants_bitwise_and_autotune(name, scheme, amr):
     """Every admissible tile shape gives the same result bit for bit (the
     per-cell operation sequence does not depend on tiling), and the autotuner
     picks one of them."""
@@ -350,7 +389,7 @@ def test_tile_variants_bitwise_and_autotune(name, amr):
     d = o.cfg.dim
     results = []
     for v in range(11):
-        h = amr.Hierarchy(o.cfg)
+        h = amr.Hierarchy(o.cfg, scheme=H.SCHEMES[scheme])
         pid, _ = H.mirror(o, h)
         try:
             h.set_tile_variant(v)

@@ -193,3 +193,86 @@ def test_shock_tube_converges_to_exact_char(seed):
         errs.append(err)
     assert errs[0] > errs[1] > errs[2]
     assert math.log2(errs[0] / errs[2]) / 2 >= 0.6, errs
+
+
+def _speed(U, d, j, gamma):
+    rho = U[0]
+    u = U[1:1 + d] / rho
+    p = (gamma - 1.0) * (U[d + 1] - 0.5 * rho * np.dot(u, u))
+    return abs(u[j]) + math.sqrt(gamma * p / rho)
+
+
+def _rusanov_copy(UL, UR, d, j, gamma):
+    """Eq. (11)-(12) from conserved edge states (test copy, plain floats)."""
+    S = max(_speed(UL, d, j, gamma), _speed(UR, d, j, gamma))
+    return 0.5 * (_flux_conserved(UR, d, j, gamma) + _flux_conserved(UL, d, j, gamma)) \
+        - 0.5 * S * (UR - UL)
+
+
+def _extreme_patch(seed):
+    """A 1D patch (8 cells + ghosts) of near-vacuum states next to fast,
+    high-pressure ones: characteristic interpolation overshoots into
+    negative density or pressure at some edges."""
+    rng = np.random.default_rng(seed)
+    N = 8 + 2 * euler.NG
+    rho = np.exp(rng.uniform(np.log(1e-3), 0.0, N))
+    p = np.exp(rng.uniform(np.log(1e-3), np.log(10.0), N))
+    u = rng.uniform(-3.0, 3.0, N)
+    return euler.conserved_from_primitive(rho, [u], p, GAMMA)
+
+
+def _char_edge_states(U):
+    """The interpolated edge states of every edge, composed from the
+    oracle's eigenvectors and WENO5-JS (no fallback)."""
+    N = U.shape[1]
+    ne = N - 2 * euler.NG + 3
+    out = []
+    for e in range(ne):
+        win = [U[:, e + k] for k in range(6)]
+        R, L = _matrices(0.5 * (win[2] + win[3]), 1, 0)
+        W = [L @ w for w in win]
+        wl = np.array([euler.weno5js(*[W[k][f] for k in range(5)], 1e-6) for f in range(3)])
+        wr = np.array([euler.weno5js(*[W[k][f] for k in (5, 4, 3, 2, 1)], 1e-6)
+                       for f in range(3)])
+        out.append((R @ wl, R @ wr, win))
+    return out
+
+
+def _physical(X):
+    p = (GAMMA - 1.0) * (X[2] - 0.5 * X[1] * (X[1] / X[0]))
+    return X[0] > 0.0 and p > 0.0
+
+
+def _fluxes_with(U, rule):
+    F = []
+    for UL, UR, win in _char_edge_states(U):
+        okL, okR = _physical(UL), _physical(UR)
+        if rule == "both" and not (okL and okR):
+            UL, UR = win[2], win[3]
+        elif rule == "side":            # planted: only the failing side falls back
+            UL = UL if okL else win[2]
+            UR = UR if okR else win[3]
+        elif rule == "wide" and not (okL and okR):   # planted: nodes i-1 and i+2
+            UL, UR = win[1], win[4]
+        F.append(_rusanov_copy(UL, UR, 1, 0, GAMMA))
+    return np.array(F).T
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_char_fallback_edge_takes_the_node_states(seed):
+    """Where an interpolated characteristic state has rho <= 0 or p <= 0 on
+    either side, the edge flux is the Rusanov flux of the two nodes' own
+    states; elsewhere it is the flux of the interpolated states.  Planted
+    readings (fall back on the failing side only; use nodes i-1, i+2) must
+    disagree at the fallback edges."""
+    U = _extreme_patch(seed)
+    got = np.array(euler.edge_fluxes_characteristic(U, 1, 0, GAMMA, 1e-6))
+    states = _char_edge_states(U)
+    bad = [not (_physical(a) and _physical(b)) for a, b, _ in states]
+    assert any(bad) and not all(bad), bad
+    want = _fluxes_with(U, "both")
+    scale = np.max(np.abs(want), axis=1, keepdims=True)
+    assert np.max(np.abs(got - want) / scale) <= 1e-12
+    for twin in ("side", "wide"):
+        diff = np.max(np.abs(got - _fluxes_with(U, twin)) / scale, axis=0)
+        assert np.max(diff[np.array(bad)]) > 1e-6, twin
