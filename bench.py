@@ -22,19 +22,31 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 
 
-def flops_per_cell_stage(d: int, stage: int) -> int:
+def flops_per_cell_stage(d: int, stage: int, scheme: str = "weno") -> int:
     """Algorithmic FP64 operations of one cell in one RK stage, counted on the
     definitions (add, mul, div, sqrt = 1; one edge and one face per cell and
-    direction): primitives 3d+4; per direction 2(d+2) WENO5-JS evaluations of
-    66 operations, two edge states of 4d+10, Rusanov 5(d+2), face flux
-    5(d+2), divergence 3(d+2); the stage combination 2 (stage 1) or 5
-    operations per variable."""
+    direction).  WENO5-JS on primitives: primitives 3d+4; per direction
+    2(d+2) WENO5-JS evaluations of 66 operations, two edge states of 4d+10,
+    Rusanov 5(d+2), face flux 5(d+2), divergence 3(d+2); the stage
+    combination 2 (stage 1) or 5 operations per variable.  Central (Eq. 8):
+    the interpolations are 4 operations and one value serves both sides.
+    Characteristic variables: no primitives; per direction the mean state
+    2(d+2), its eigensystem 3d+14, six node projections of 4d+9, 2(d+2)
+    WENO5-JS evaluations, two back projections of 4d+10, two positivity
+    tests of 3d+4, two conserved-state fluxes with signal speed of 4d+12,
+    then Rusanov, face flux and divergence as above."""
     nv = d + 2
-    weno = 2 * nv * 66
-    flux = 2 * (4 * d + 10) + 5 * nv
-    per_dir = weno + flux + 5 * nv + 3 * nv
+    tail = 5 * nv + 5 * nv + 3 * nv
+    if scheme == "char":
+        per_dir = (2 * nv + (3 * d + 14) + 6 * (4 * d + 9) + 2 * nv * 66 + 2 * (4 * d + 10)
+                   + 2 * (3 * d + 4) + 2 * (4 * d + 12) + tail)
+        prim = 0
+    else:
+        interp = nv * 4 if scheme == "central" else 2 * nv * 66
+        per_dir = interp + 2 * (4 * d + 10) + tail
+        prim = 3 * d + 4
     combine = (2 if stage == 1 else 5) * nv
-    return (3 * d + 4) + d * per_dir + combine
+    return prim + d * per_dir + combine
 
 
 def bytes_per_cell_stage(d: int, stage: int) -> int:
@@ -98,7 +110,7 @@ def host_cpu() -> str:
     return platform.processor() or "unknown CPU"
 
 
-def cpu_baseline(cfg, seed: int):
+def cpu_baseline(cfg, seed: int, scheme: str = "weno"):
     """The oracle, as it stands, on a bounded sample of the workload: one
     SSP-RK3 step over a hierarchy it builds itself from the same generator
     and seed.  In 3D the sample is the benchmark layout (patches 32/16/16/8,
@@ -110,7 +122,7 @@ def cpu_baseline(cfg, seed: int):
     gen = workloads.initial_data(cfg, seed)
     if cfg.dim == 3:
         sc = workloads.c5_sample_config().replace(ic=cfg.ic, cfl=cfg.cfl, gamma=cfg.gamma)
-        o = OracleAMR(sc)
+        o = OracleAMR(sc, scheme=scheme)
         for k in o.forest.keys():
             o.set_initial(k, gen)
         for keys in workloads.blast_refinements(sc, seed):
@@ -119,7 +131,7 @@ def cpu_baseline(cfg, seed: int):
                 f"{sc.patch_cells}, {sc.max_levels} levels) over a {sc.base_cells}^3 base "
                 f"refined around the first blast of the same generator ({cfg.ic}, seed {seed})")
     elif cfg.base_cells ** cfg.dim <= ORACLE_MAX_BASE_CELLS:
-        o = OracleAMR(cfg)
+        o = OracleAMR(cfg, scheme=scheme)
         o.init_from_ic(gen)
         what = f"one SSP-RK3 step of the oracle over the {cfg.name} initial hierarchy (seed {seed})"
     else:
@@ -370,6 +382,7 @@ def learned_vs_plain(cfg, args):
     return {"unit": "s wall per unit simulated time", "steps": args.learned_steps,
             "policies": {k: {"wall_per_tsim": v["wall_per_tsim"], "coverage": v["coverage"],
                              "regrids": v["regrids"], "fallbacks": v["fallbacks"],
+                             "capacity_retries": v["capacity_retries"],
                              "cell_updates": v["cell_updates"], "t_sim": v["t_sim"]}
                          for k, v in res.items()},
             "learned_speedup_vs": {k: v["wall_per_tsim"] / L for k, v in res.items()},
@@ -428,6 +441,9 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=None,
                     help="initial-data seed (default: 1000 * config number + 1)")
     ap.add_argument("--exec", dest="exec_mode", default="batched", choices=["batched", "per_patch"])
+    ap.add_argument("--scheme", default="weno", choices=["weno", "central", "char"],
+                    help="edge interpolation: WENO5-JS of the primitives (default), the central "
+                         "interpolation of Eq. (8), or WENO5-JS of characteristic variables")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=100)
     ap.add_argument("--no-autotune", action="store_true")
@@ -502,10 +518,13 @@ def main() -> int:
         num = args.config[1:] if args.config[:1] == "c" and args.config[1:].isdigit() else "2"
         args.seed = workloads.seed_for(int(num), 1)
     mode = amr.EXEC_BATCHED if args.exec_mode == "batched" else amr.EXEC_PER_PATCH
-    h = amr.Hierarchy(cfg, exec_mode=mode)
+    scheme = {"weno": amr.SCHEME_WENO, "central": amr.SCHEME_CENTRAL,
+              "char": amr.SCHEME_CHAR}[args.scheme]
+    t_init = time.perf_counter()
+    h = amr.Hierarchy(cfg, exec_mode=mode, scheme=scheme)
     amr.init_from_ic(h, workloads.initial_data(cfg, args.seed))
     log(f"[bench] {cfg.name}: initial hierarchy {h.counts()} patches (active, leaf), "
-        f"{h.leaf_cells()} leaf cells")
+        f"{h.leaf_cells()} leaf cells ({time.perf_counter() - t_init:.1f} s)")
     tile = None
     if args.tile is not None:
         h.set_tile_variant(args.tile)
@@ -540,6 +559,7 @@ def main() -> int:
         per = {}
         for g in (False, True):
             h.set_graph(g)
+            advance(2, False)  # records the two step graphs (one per rate slot)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             advance(16, False)
@@ -550,12 +570,18 @@ def main() -> int:
             f"{'graph' if use_graph else 'eager'}")
     h.set_graph(use_graph and mode == amr.EXEC_BATCHED)
     # pass 1: whole-job throughput (step graphs replayed, no instrumentation)
+    rec0 = h.graph_records()
+    regrids0 = nstep
     t0 = time.perf_counter()
     cells = advance(args.steps, True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s")
+    rec_timed = h.graph_records() - rec0
+    regrids_timed = (nstep // cfg.regrid_interval - regrids0 // cfg.regrid_interval
+                     if cfg.regrid_interval > 0 else 0)
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s ({regrids_timed} regrids, "
+        f"{rec_timed} step graphs recorded)")
     # pass 2: the fused stage kernel timed with HIP events around every launch
     # (eager launches on the same stream; kernel work is identical)
     psteps = min(args.steps, args.profile_steps)
@@ -570,7 +596,7 @@ def main() -> int:
     if h.check() != 0:
         log("[bench] WARNING: non-physical cells after the run")
     d = cfg.dim
-    f_step = sum(flops_per_cell_stage(d, s) for s in (1, 2, 3))
+    f_step = sum(flops_per_cell_stage(d, s, args.scheme) for s in (1, 2, 3))
     b_step = sum(bytes_per_cell_stage(d, s) for s in (1, 2, 3))
     # every timed step launches the stage kernel once per stage over all leaf
     # cells (batched) or once per tile group (per-patch): totals per step
@@ -599,7 +625,10 @@ def main() -> int:
                         f"{'periodic' if all(cfg.periodic) else 'mixed bc'}, ic {cfg.ic} "
                         f"seed {args.seed}, CFL {cfg.cfl}, regrid every {cfg.regrid_interval}",
             "exec": args.exec_mode,
+            "scheme": args.scheme,
             "step_graph": bool(use_graph and mode == amr.EXEC_BATCHED),
+            "regrids_timed": regrids_timed,
+            "step_graphs_recorded_timed": rec_timed,
             "tile": None if tile is None else {"variant": tile[0], "extent": tile[1],
                                                "threads": tile[2],
                                                "xy_edges_in_one_sweep": tile[0] >= 8},
@@ -607,12 +636,16 @@ def main() -> int:
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_stage (fused WENO5-JS + Rusanov + Eq. (9) divergence + RK combine)",
+            "kernel": "k_stage (fused " + {"weno": "WENO5-JS of the primitives",
+                                           "central": "central interpolation (Eq. (8))",
+                                           "char": "WENO5-JS of characteristic variables"}[
+                args.scheme] + " + Rusanov + Eq. (9) divergence + RK combine)",
             "achieved": achieved_tf,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tf / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": measured_traffic(None if tile is None else tile[0], cells_per_launch),
+            "traffic": measured_traffic(None if tile is None or args.scheme != "weno" else tile[0],
+                                        cells_per_launch),
             "launches": launches,
             "avg_launch_ms": ms / max(1, launches),
             "cells_per_launch": cells_per_launch,
@@ -633,12 +666,12 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.seed)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.seed, args.scheme)
         if out["cpu_baseline"] is None:
             log(f"[bench] no cpu_baseline: {cfg.base_cells}^{cfg.dim} base cells is beyond the "
                 f"oracle's bounded sample")
     if not args.no_learned and mode == amr.EXEC_BATCHED and cfg.dim >= 2 \
-            and cfg.regrid_interval > 2:
+            and cfg.regrid_interval > 2 and args.scheme == "weno":
         out["learned_vs_plain"] = learned_vs_plain(cfg, args)
     print(json.dumps(out), flush=True)
     return 0

@@ -332,13 +332,20 @@ amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const 
                                  float* d_dev);
 
 /* hipGraph replay of amr_step in batched mode (default off): the kernels of
- * one step are captured once and replayed until the next regrid that changes
- * the mesh, or a mode change; the graph holds kernel nodes only.  Results are
- * identical.  Off by default because a step is a few launches of several
- * microseconds each, whose CPU launch cost eager launching already hides;
- * callers that cannot afford the CPU time per step (or capture the step into
- * their own graphs) turn it on. */
+ * one step are captured once (two graphs, one per CFL-rate slot) and
+ * replayed; the graph holds kernel nodes only.  Batched launches of the
+ * step's kernels read their work lists and live counts from a device list
+ * directory that regrids rewrite, and a recorded launch holds a quarter
+ * plus 256 more blocks than its list had (blocks past the live count exit),
+ * so a regrid does not invalidate the graphs unless a list outgrows its
+ * recorded grid; then the next step records them again (with the fused
+ * halo off, the explicit ghost fill is sized by the leaf count and every
+ * mesh change re-records them).  A change of tile variant, execution mode,
+ * halo mode or dt pointer re-records them.  Enabling an enabled graph mode
+ * keeps the recorded graphs.  Results are identical to eager launches. */
 amr_status amr_set_graph(amr_hierarchy* h, int enable);
+/* Number of step graphs recorded since creation (test and profiling hook). */
+amr_status amr_graph_records(const amr_hierarchy* h, int* recorded);
 
 /* Tile variants of the fused stage kernel (cells per tile and block size):
  * 0: 16 (1D, 64 threads), 1: 8 (1D), 2: 16x16 (2D, 320), 3: 16x8 (2D, 192),

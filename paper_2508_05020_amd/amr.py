@@ -117,6 +117,7 @@ _sigs = {
     "amr_set_fused_halo": [_H, C.c_int],
     "amr_set_tag_buffer": [_H, C.c_int],
     "amr_set_graph": [_H, C.c_int],
+    "amr_graph_records": [_H, _P(C.c_int)],
     "amr_set_tile_variant": [_H, C.c_int],
     "amr_get_tile_variant": [_H, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)],
     "amr_autotune": [_H, C.c_int, _P(C.c_int), _P(C.c_float)],
@@ -433,6 +434,11 @@ class Hierarchy:
 
     def set_graph(self, enable: bool):
         self._ok(_lib.amr_set_graph(self.h, 1 if enable else 0))
+
+    def graph_records(self) -> int:
+        n = C.c_int()
+        self._ok(_lib.amr_graph_records(self.h, C.byref(n)))
+        return n.value
 
     def set_fused_halo(self, enable: bool):
         self._ok(_lib.amr_set_fused_halo(self.h, 1 if enable else 0))

@@ -53,10 +53,15 @@ struct DevMesh {
   const int* map;      // all levels' patch maps
 };
 
-// Work lists, all resident in one device int buffer.
+// Work lists, all resident in one device int buffer.  `dir` (null for lists
+// outside it) is the list's entry {offset into the buffer, count} of the
+// device list directory, which batched launches of the step's kernels read
+// at run time, so that a recorded step stays valid across regrids as long
+// as each list fits the grid it was recorded with.
 struct ListView {
   const int* ptr;
   int count;
+  const int* dir = nullptr;
 };
 
 // Launch wrappers implemented in kernels.hip.
@@ -66,8 +71,11 @@ struct Kernels {
   static void fill(const DevMesh& m, double* U, const int* list, int count, int* err,
                    bool coarse_only, hipStream_t s);
   // prolonged ghost cells only, over (pid, ghost region) pairs
-  static void fill_cf(const DevMesh& m, double* U, const int* list, int count, int* err,
-                      hipStream_t s);
+  // dir (nullable): list directory entry; with it `list` is the list buffer
+  // and the list and its live count are read at run time, and `count` only
+  // sizes the grid (at least the live count: one block per item)
+  static void fill_cf(const DevMesh& m, double* U, const int* list, int count, const int* dir,
+                      int* err, hipStream_t s);
   // fuse = halo nodes outside the patch with a same-level source are read
   // from that source by the kernel itself; the others (prolonged) come from
   // ghost layers filled before by fill_cf
@@ -77,7 +85,7 @@ struct Kernels {
   // lam_in (stage 1 only, optional): take dt = CFL / *lam_in instead of *dt,
   // write it to *dt_out and clear *lam_next (the slot stage 3 accumulates in)
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
-                    double* out, double* fr, const int* tiles, int count,
+                    double* out, double* fr, const int* tiles, int count, const int* dir,
                     const double* dt, bool fuse, unsigned long long* lam_next,
                     const uint8_t* cfmask, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr, const unsigned long long* lam_in = nullptr,
@@ -88,12 +96,15 @@ struct Kernels {
   // refluxing and the restriction of the two finest levels in one launch:
   // reflux items, level-lup patches with children (plist), level-lup leaves
   // without coarse/fine faces (slist); lup = finest level - 1
+  // dir (nullable): the directory entries of the three lists, in order;
+  // with it the list pointers are the list buffer, the live counts are read
+  // at run time and nref + npair + nsingle only sizes the grid
   static void post(const DevMesh& m, int mode, double* out, const double* fr, const int* rlist,
                    int nref, const int* plist, int npair, const int* slist, int nsingle,
-                   int lup, const double* dt, double w, unsigned long long* lam_next,
-                   hipStream_t s);
+                   const int* dir, int lup, const double* dt, double w,
+                   unsigned long long* lam_next, hipStream_t s);
   static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
-                             hipStream_t s);
+                             const int* dir, hipStream_t s);
   static void max_rate(const DevMesh& m, const double* U, const int* list, int count,
                        unsigned long long* lam_bits, hipStream_t s);
   static void zero_u64(unsigned long long* p, hipStream_t s);

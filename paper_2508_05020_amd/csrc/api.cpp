@@ -39,6 +39,10 @@ struct StateError : std::runtime_error {
     }                                                                        \
   } while (0)
 
+// entries of the device list directory
+enum { kDirCf = 0, kDirTiles = 1, kDirReflux = 2, kDirPairs = 3, kDirSingles = 4, kDirRestr = 5,
+       kDirEntries = kDirRestr + amr::kMaxLev };
+
 }  // namespace
 
 struct amr_hierarchy {
@@ -56,13 +60,19 @@ struct amr_hierarchy {
   int exec_mode = AMR_EXEC_BATCHED;
   bool fuse_halo = true;  // stage kernel gathers halos itself (no fill pass)
   // hipGraphs of one batched step (dt + 3 stages), one per parity of the CFL
-  // rate double buffer, valid until the next regrid or mode change
+  // rate double buffer.  Their launches read the work lists and counts from
+  // the list directory, so a regrid leaves them valid while every list fits
+  // the grid it was recorded with (rec_count: the counts at recording, see
+  // grid_count); a tile, mode or configuration change invalidates them.
   bool use_graph = false;
+  bool capturing = false;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t step_exec[2] = {nullptr, nullptr};
   const double* step_exec_dt[2] = {nullptr, nullptr};
   bool step_exec_valid = false;
   bool step_exec_ok[2] = {false, false};
+  int rec_count[2][kDirEntries] = {};
+  int step_records = 0;  // step graphs recorded so far
   // CFL rate of U^n: slot lam_cur holds it when lam_valid; the step being
   // run accumulates the next one into the other slot (slot 2: amr_compute_dt)
   int lam_cur = 0;
@@ -90,6 +100,12 @@ struct amr_hierarchy {
   int* d_flags = nullptr;  // [0] fill/prolong error, [1] nonphysical count
   int* d_lists = nullptr;
   long long lists_cap = 0;
+  // list directory: {offset into d_lists, count} of the lists the step's
+  // kernels take (entries kDirCf, kDirTiles, kDirReflux, kDirPairs,
+  // kDirSingles, kDirRestr + level), rewritten with the lists; batched
+  // launches read it, so a recorded step survives a regrid
+  int* d_dir = nullptr;
+  int* h_dir = nullptr;  // pinned staging of the directory
   int* d_pairs = nullptr;
   long long pairs_cap = 0;
   // pinned host staging for table/list uploads (reused; every regrid first
@@ -168,6 +184,8 @@ struct amr_hierarchy {
     h_stage = nullptr;
     if (h_req) (void)hipHostFree(h_req);
     h_req = nullptr;
+    if (h_dir) (void)hipHostFree(h_dir);
+    h_dir = nullptr;
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     ev_pool.clear();
     for (void* p : owned) {
@@ -218,6 +236,7 @@ std::vector<CopyRun> copy_runs(const amr_hierarchy* h, const int* pids, int npat
   }
   return runs;
 }
+
 
 void validate_config(const amr_config& c) {
   if (c.dim < 1 || c.dim > 3) throw ArgError("dim must be 1, 2 or 3");
@@ -456,10 +475,11 @@ void sync_tables(amr_hierarchy* h, bool full) {
     for (int k = 0; k < f.nchild[pid]; ++k) all_leaves &= f.is_leaf(f.child[(size_t)pid * f.maxc + k]);
     if (all_leaves) L.push_back(pid);
   }
+  // (leaf, tile) items in brick order (see Forest::leaves_brick_order); the
+  // stage kernel's results do not depend on the item order
   const int t0 = begin_list();
   h->leaf_cells = 0;
-  for (int pid : order) {
-    if (!f.is_leaf(pid)) continue;
+  for (int pid : f.leaves_brick_order()) {
     h->leaf_cells += ipow(f.n[f.level[pid]], f.dim);
     const int nt = Kernels::tiles_per_patch(h->dm.tile, f.n[f.level[pid]]);
     for (int t = 0; t < nt; ++t) {
@@ -528,17 +548,36 @@ void sync_tables(amr_hierarchy* h, bool full) {
   if (!L.empty())
     HIP_OK(hipMemcpyAsync(h->d_lists, sl, L.size() * sizeof(int), hipMemcpyHostToDevice,
                           h->stream));
+  const int* dd = h->d_dir;
   h->all = {h->d_lists + a0, a1 - a0};
   h->leaves = {h->d_lists + a1, c0 - a1};
-  h->cfregions = {h->d_lists + c0, (k0 - c0) / 2};
+  h->cfregions = {h->d_lists + c0, (k0 - c0) / 2, dd + 2 * kDirCf};
   h->cands = {h->d_lists + k0, t0 - k0};
-  h->tiles = {h->d_lists + t0, (r0 - t0) / 2};
-  h->reflux = {h->d_lists + r0, nref};
-  h->post_pairs = {h->d_lists + pp0, ps0 - pp0};
-  h->post_singles = {h->d_lists + ps0, ps1 - ps0};
+  h->tiles = {h->d_lists + t0, (r0 - t0) / 2, dd + 2 * kDirTiles};
+  h->reflux = {h->d_lists + r0, nref, dd + 2 * kDirReflux};
+  h->post_pairs = {h->d_lists + pp0, ps0 - pp0, dd + 2 * kDirPairs};
+  h->post_singles = {h->d_lists + ps0, ps1 - ps0, dd + 2 * kDirSingles};
   for (int l = 0; l < f.nlev; ++l) {
-    h->restr[l] = {h->d_lists + rs[l], rs[l + 1] - rs[l]};
+    h->restr[l] = {h->d_lists + rs[l], rs[l + 1] - rs[l], dd + 2 * (kDirRestr + l)};
     h->fresh[l] = {h->d_lists + ns[l], ns[l + 1] - ns[l]};
+  }
+  {
+    // the previous directory upload has completed: every regrid drains the
+    // stream before rebuilding the lists
+    int* hd = h->h_dir;
+    std::fill(hd, hd + 2 * kDirEntries, 0);
+    auto put = [&](int e, const amr::ListView& lv) {
+      hd[2 * e] = (int)(lv.ptr - h->d_lists);
+      hd[2 * e + 1] = lv.count;
+    };
+    put(kDirCf, h->cfregions);
+    put(kDirTiles, h->tiles);
+    put(kDirReflux, h->reflux);
+    put(kDirPairs, h->post_pairs);
+    put(kDirSingles, h->post_singles);
+    for (int l = 0; l < f.nlev; ++l) put(kDirRestr + l, h->restr[l]);
+    HIP_OK(hipMemcpyAsync(h->d_dir, hd, 2 * kDirEntries * sizeof(int), hipMemcpyHostToDevice,
+                          h->stream));
   }
   HIP_OK(hipMemcpyAsync(h->d_active_leaf, sa, mp, hipMemcpyHostToDevice, h->stream));
   // coarse/fine faces of coarse-side leaves, then the faces whose flux
@@ -583,6 +622,31 @@ void over_list(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F lau
   h->check_launch();
 }
 
+// Grid size (in work items) of a batched launch over a directory list: the
+// live count, or while a step graph is recorded the count with headroom, so
+// that the recorded launch still covers the list after regrids that grow it
+// by up to a quarter plus 256 items (amr_step records the graph again when a
+// list outgrows it).  The blocks past the live count exit at once.
+int headroom(int count) { return count + count / 4 + 256; }
+
+int grid_count(const amr_hierarchy* h, const amr::ListView& lv) {
+  return h->capturing ? headroom(lv.count) : lv.count;
+}
+
+// The step's kernels: in batched mode one launch that reads the list and its
+// live count from the list directory (launch(list buffer, grid count,
+// directory entry)); per-patch mode as over_list.
+template <typename F>
+void over_list_dir(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F launch) {
+  if (h->exec_mode == AMR_EXEC_BATCHED) {
+    launch(h->d_lists, grid_count(h, lv), lv.dir);
+  } else {
+    for (int i = 0; i < lv.count; ++i)
+      launch(lv.ptr + (long long)i * stride_ints, 1, (const int*)nullptr);
+  }
+  h->check_launch();
+}
+
 void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_only = false) {
   over_list(h, lv, 1, [&](const int* p, int c) {
     Kernels::fill(h->dm, h->U[buf], p, c, h->d_flags, coarse_only, h->stream);
@@ -593,8 +657,8 @@ void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_onl
 // halo only the prolonged ones
 void stage_fill(amr_hierarchy* h, int buf) {
   if (h->fuse_halo) {
-    over_list(h, h->cfregions, 2, [&](const int* p, int c) {
-      Kernels::fill_cf(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+    over_list_dir(h, h->cfregions, 2, [&](const int* p, int c, const int* dir) {
+      Kernels::fill_cf(h->dm, h->U[buf], p, c, dir, h->d_flags, h->stream);
     });
   } else {
     do_fill(h, buf, h->leaves);
@@ -603,8 +667,8 @@ void stage_fill(amr_hierarchy* h, int buf) {
 
 void do_restrict(amr_hierarchy* h, int buf) {
   for (int l = h->forest.nlev - 1; l >= 1; --l)
-    over_list(h, h->restr[l], 1, [&](const int* p, int c) {
-      Kernels::restrict_level(h->dm, h->U[buf], p, c, h->stream);
+    over_list_dir(h, h->restr[l], 1, [&](const int* p, int c, const int* dir) {
+      Kernels::restrict_level(h->dm, h->U[buf], p, c, dir, h->stream);
     });
 }
 
@@ -620,25 +684,25 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
   stage_fill(h, s);
   const Kernels::TileVariant tv = Kernels::variant(h->dm.tile);
   const int tcells = tv.tx * tv.ty * tv.tz;
-  over_list(h, h->tiles, 2, [&](const int* p, int c) {
+  over_list_dir(h, h->tiles, 2, [&](const int* p, int c, const int* dir) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->profiling) h->prof_pair(&a, &b, (long long)c * tcells);
-    Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dt, h->fuse_halo,
+    Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dir, dt, h->fuse_halo,
                    (stage == 3 || lam_in) ? lam_next : nullptr, h->d_cfmask, h->stream, a, b,
                    lam_in, dt_out);
   });
   if (h->exec_mode == AMR_EXEC_BATCHED) {
     // refluxing and the restriction of the two finest levels share a launch;
-    // coarser levels follow, finest first
+    // coarser levels follow, finest first (lists and counts from the list
+    // directory: the three post-stage entries are consecutive)
     const int lup = h->forest.nlev - 2;
-    Kernels::post(h->dm, stage, h->U[d], h->fr, h->reflux.ptr, h->reflux.count,
-                  h->post_pairs.ptr, h->post_pairs.count, h->post_singles.ptr,
-                  h->post_singles.count, lup, dt, w[stage], stage == 3 ? lam_next : nullptr,
-                  h->stream);
+    Kernels::post(h->dm, stage, h->U[d], h->fr, h->d_lists, grid_count(h, h->reflux), h->d_lists,
+                  grid_count(h, h->post_pairs), h->d_lists, grid_count(h, h->post_singles),
+                  h->reflux.dir, lup, dt, w[stage], stage == 3 ? lam_next : nullptr, h->stream);
     h->check_launch();
     for (int l = lup - 1; l >= 1; --l)
-      over_list(h, h->restr[l], 1, [&](const int* p, int c) {
-        Kernels::restrict_level(h->dm, h->U[d], p, c, h->stream);
+      over_list_dir(h, h->restr[l], 1, [&](const int* p, int c, const int* dir) {
+        Kernels::restrict_level(h->dm, h->U[d], p, c, dir, h->stream);
       });
   } else {
     over_list(h, h->reflux, 2, [&](const int* p, int c) {
@@ -687,8 +751,8 @@ void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_
   // none); else full fills
   const bool fuse = h->fuse_halo;
   if (fuse) {
-    over_list(h, h->cfregions, 2, [&](const int* p, int c) {
-      Kernels::fill_cf(h->dm, h->U[buf], p, c, h->d_flags, h->stream);
+    over_list_dir(h, h->cfregions, 2, [&](const int* p, int c, const int* dir) {
+      Kernels::fill_cf(h->dm, h->U[buf], p, c, dir, h->d_flags, h->stream);
     });
   } else {
     do_fill(h, buf, h->leaves);
@@ -744,7 +808,10 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
     return AMR_E_MESH;
   }
   h->last_created = created;
-  h->step_exec_valid = false;
+  // the recorded step graphs stay valid: their launches read the lists and
+  // counts from the list directory that sync_tables rewrites (the explicit
+  // ghost fill of the unfused path is sized by the leaf count)
+  if (!h->fuse_halo) h->step_exec_valid = false;
   h->lam_valid = false;
   sync_tables(h, false);
   // a missing prolongation source (impossible on a valid mesh) raises the
@@ -850,6 +917,8 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
     const long long regions = ipow(3, cfg->dim) - 1;
     h->lists_cap = 2 * tiles + (9 + 2 * regions) * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
+    h->d_dir = (int*)h->dev_alloc(2 * kDirEntries * sizeof(int));
+    HIP_OK(hipHostMalloc((void**)&h->h_dir, 2 * kDirEntries * sizeof(int), hipHostMallocDefault));
     h->pairs_cap = mp * (6 + f.maxc) + 2 * (long long)f.map.size() + 64;
     h->pairs_cap = std::min<long long>(h->pairs_cap, 64LL << 20);
     h->d_pairs = (int*)h->dev_alloc(h->pairs_cap * 2 * sizeof(int));
@@ -1095,8 +1164,8 @@ amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
   if (!h || !buf_ok(buf) || !rhs_dev) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
     stage_fill(h, buf);
-    over_list(h, h->tiles, 2, [&](const int* p, int c) {
-      Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, h->d_dt,
+    over_list_dir(h, h->tiles, 2, [&](const int* p, int c, const int* dir) {
+      Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, dir, h->d_dt,
                      h->fuse_halo, nullptr, h->d_cfmask, h->stream);
     });
     over_list(h, h->reflux, 2, [&](const int* p, int c) {
@@ -1137,22 +1206,30 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
         h->step_exec_ok[0] = h->step_exec_ok[1] = false;
         h->step_exec_valid = true;
       }
-      if (!h->step_exec_ok[cur] || h->step_exec_dt[cur] != dt) {
+      // a list that outgrew the grid its launch was recorded with
+      bool fits = true;
+      for (int e = 0; e < kDirEntries; ++e)
+        fits = fits && h->h_dir[2 * e + 1] <= headroom(h->rec_count[cur][e]);
+      if (!h->step_exec_ok[cur] || h->step_exec_dt[cur] != dt || !fits) {
         if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipStream_t user = h->stream;
         h->stream = h->cap_stream;
         hipGraph_t g = nullptr;
         HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        h->capturing = true;
         try {
           do_step(h, dt, cur);
         } catch (...) {
+          h->capturing = false;
           (void)hipStreamEndCapture(h->stream, &g);
           if (g) (void)hipGraphDestroy(g);
           h->stream = user;
           throw;
         }
+        h->capturing = false;
         HIP_OK(hipStreamEndCapture(h->stream, &g));
         h->stream = user;
+        for (int e = 0; e < kDirEntries; ++e) h->rec_count[cur][e] = h->h_dir[2 * e + 1];
         if (h->step_exec[cur]) HIP_OK(hipGraphExecDestroy(h->step_exec[cur]));
         h->step_exec[cur] = nullptr;
         const hipError_t e = hipGraphInstantiate(&h->step_exec[cur], g, nullptr, nullptr, 0);
@@ -1160,6 +1237,7 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
         HIP_OK(e);
         h->step_exec_ok[cur] = true;
         h->step_exec_dt[cur] = dt;
+        ++h->step_records;
       }
       HIP_OK(hipGraphLaunch(h->step_exec[cur], h->stream));
     }
@@ -1169,10 +1247,18 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
   });
 }
 
+amr_status amr_graph_records(const amr_hierarchy* h, int* recorded) {
+  if (!h || !recorded) return AMR_E_ARG;
+  *recorded = h->step_records;
+  return AMR_OK;
+}
+
 amr_status amr_set_graph(amr_hierarchy* h, int enable) {
   if (!h) return AMR_E_ARG;
-  h->use_graph = enable != 0;
-  h->step_exec_valid = false;
+  if (h->use_graph != (enable != 0)) {
+    h->use_graph = enable != 0;
+    h->step_exec_valid = false;
+  }
   return AMR_OK;
 }
 
@@ -1288,12 +1374,15 @@ amr_status amr_autotune(amr_hierarchy* h, int reps, int* best, float* best_ms) {
       h->dm.tile = v;
       h->last_created.clear();
       sync_tables(h, false);
-      Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->tiles.ptr,
-                     h->tiles.count, h->d_dt, h->fuse_halo, nullptr, h->d_cfmask, h->stream);
+      // the launch the batched step makes (list and count from the directory)
+      Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->d_lists,
+                     h->tiles.count, h->tiles.dir, h->d_dt, h->fuse_halo, nullptr, h->d_cfmask,
+                     h->stream);
       HIP_OK(hipEventRecord(e0, h->stream));
       for (int r = 0; r < reps; ++r)
-        Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->tiles.ptr,
-                       h->tiles.count, h->d_dt, h->fuse_halo, nullptr, h->d_cfmask, h->stream);
+        Kernels::stage(h->dm, amr::kModeRHS, h->U[0], h->U[0], scratch, h->fr, h->d_lists,
+                       h->tiles.count, h->tiles.dir, h->d_dt, h->fuse_halo, nullptr,
+                       h->d_cfmask, h->stream);
       HIP_OK(hipEventRecord(e1, h->stream));
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0.f;

@@ -208,15 +208,19 @@ __device__ __forceinline__ void block_max_atomic(unsigned long long best,
   }
 }
 
-// Work item of this block when the grid is a whole number of groups of kXcds
-// blocks.  Workgroups are dealt to the chip's XCDs in turn (block b runs on
-// XCD b mod kXcds), and each XCD has its own L2; the mapping gives every XCD
-// one contiguous run of the work list, so tiles of one patch and of
-// neighbouring patches (the list is in level, z, y, x order), which read
-// each other's cells as halos, share an L2.
+// Work item of this block.  Workgroups are dealt to the chip's XCDs in
+// turn (block b runs on XCD b mod kXcds) and each XCD has its own L2: XCD x
+// takes the contiguous items [x per, (x + 1) per), per = ceil(count /
+// kXcds), in dispatch order, so tiles of one patch and of neighbouring
+// patches (the list is in brick order), which read each other's cells as
+// halos, share an L2.  The grid holds at least kXcds per blocks; it may hold
+// more (a launch recorded for a longer list), and a block without an item
+// gets -1.
 __device__ __forceinline__ int xcd_item(int count) {
-  const int per_xcd = (int)gridDim.x / kXcds;
-  return ((int)blockIdx.x % kXcds) * per_xcd + (int)blockIdx.x / kXcds;
+  const int per = (count + kXcds - 1) / kXcds;
+  const int k = (int)blockIdx.x / kXcds;
+  const int item = ((int)blockIdx.x % kXcds) * per + k;
+  return (k < per && item < count) ? item : -1;
 }
 
 }  // namespace

@@ -438,4 +438,57 @@ std::vector<int> Forest::sorted_active() const {
 }
 
 
+namespace {
+// Morton code of a patch position: the bits of x, y, z interleaved, x
+// lowest (13 bits per coordinate).
+uint64_t morton(const int* c, int dim) {
+  uint64_t m = 0;
+  for (int b = 0; b < 13; ++b)
+    for (int j = 0; j < dim; ++j) m |= (uint64_t)((c[j] >> b) & 1) << (b * dim + j);
+  return m;
+}
+}  // namespace
+
+std::vector<int> Forest::leaves_brick_order() const {
+  // (level, Morton code, pid) packed into one key: level in bits 60..63, the
+  // code in bits 21..59 (13 bits per coordinate), the pid in bits 0..20;
+  // else the comparator on (level, code, pid)
+  std::vector<int> out;
+  bool packed = max_patches <= (1 << 21) && nlev <= 16;
+  for (int l = 0; l < nlev; ++l) packed &= np[l] <= (1 << 13);
+  if (packed) {
+    std::vector<uint64_t> keys;
+    for (int pid = 0; pid < max_patches; ++pid) {
+      if (!active[pid] || nchild[pid]) continue;
+      keys.push_back(((uint64_t)level[pid] << 60) | (morton(&coord[3 * pid], dim) << 21) |
+                     (uint64_t)pid);
+    }
+    if (keys.size() < 4096) {
+      std::sort(keys.begin(), keys.end());
+    } else {
+      // LSD radix sort on bits 21..63, 16-bit digits (the keys are distinct)
+      std::vector<uint64_t> tmp(keys.size());
+      std::vector<uint32_t> cnt(65537);
+      for (const int sh : {21, 37, 53}) {
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (const uint64_t k : keys) ++cnt[((k >> sh) & 0xffffu) + 1];
+        for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+        for (const uint64_t k : keys) tmp[cnt[(k >> sh) & 0xffffu]++] = k;
+        keys.swap(tmp);
+      }
+    }
+    out.reserve(keys.size());
+    for (uint64_t k : keys) out.push_back((int)(k & ((1u << 21) - 1)));
+    return out;
+  }
+  for (int pid = 0; pid < max_patches; ++pid)
+    if (active[pid] && !nchild[pid]) out.push_back(pid);
+  std::sort(out.begin(), out.end(), [&](int a, int b) {
+    if (level[a] != level[b]) return level[a] < level[b];
+    const uint64_t ma = morton(&coord[3 * a], dim), mb = morton(&coord[3 * b], dim);
+    return ma != mb ? ma < mb : a < b;
+  });
+  return out;
+}
+
 }  // namespace amr

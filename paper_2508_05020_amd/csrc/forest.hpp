@@ -94,6 +94,10 @@ class Forest {
 
   // Active pids sorted by (level, z, y, x).
   std::vector<int> sorted_active() const;
+  // Leaves by level, then in Morton order of their positions: consecutive
+  // leaves of a level form compact bricks, so stage tiles that run at the
+  // same time on one XCD read each other's cells as halos.
+  std::vector<int> leaves_brick_order() const;
 
  private:
   int alloc(int l, const int c[3], int par);

@@ -79,13 +79,12 @@ __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
 // position (after the physical-boundary clamp) holds no same-level patch, so
 // every cell of the region is prolonged from level l-1.
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m, double* __restrict__ U,
-                                                const int* __restrict__ list, int count,
-                                                int* __restrict__ err) {
+__device__ __forceinline__ void fill_cf_region(const DevMesh& m, double* __restrict__ U,
+                                               const int* __restrict__ list, int item,
+                                               int* __restrict__ err) {
   constexpr int NV = D + 2;
-  if ((int)blockIdx.x >= count) return;
-  const int pid = list[2 * blockIdx.x];
-  const int code = list[2 * blockIdx.x + 1];
+  const int pid = list[2 * item];
+  const int code = list[2 * item + 1];
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n, full = L.full;
@@ -118,6 +117,22 @@ __global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m, double* __restrict__ 
   }
 }
 
+// One block per region.  With `dir` (batched launches) the list is
+// list + dir[0] and the count dir[1], read at run time (the grid may hold
+// more blocks than regions).
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m,
+                                                double* __restrict__ U,
+                                                const int* __restrict__ list, int count,
+                                                const int* __restrict__ dir,
+                                                int* __restrict__ err) {
+  if (dir) {
+    list += dir[0];
+    count = dir[1];
+  }
+  if ((int)blockIdx.x < count) fill_cf_region<D, NT>(m, U, list, blockIdx.x, err);
+}
+
 // The same regions by coarse cell (2D and 3D).  A region's start and extent
 // are even in every dimension, so its fine cells come in aligned blocks of
 // 2^D, and both cells of an aligned pair have the same coarse cell also
@@ -130,13 +145,11 @@ __global__ __launch_bounds__(NT) void k_fill_cf(DevMesh m, double* __restrict__ 
 // spreads all their coarse cells over its lanes: a 3D region covers as few
 // as 8 coarse cells (a corner).
 template <int D, int NT, int G>
-__global__ __launch_bounds__(NT) void k_fill_cf_coarse(DevMesh m, double* __restrict__ U,
-                                                       const int* __restrict__ list, int count,
-                                                       int* __restrict__ err) {
+__device__ __forceinline__ void fill_cf_coarse_group(const DevMesh& m, double* __restrict__ U,
+                                                     const int* __restrict__ list, int count,
+                                                     int first, int* __restrict__ err,
+                                                     int* s_pid, int* s_code, int* s_pre) {
   constexpr int NV = D + 2, NS = 2 * D + 1, NF = 1 << D;
-  __shared__ int s_pid[G], s_code[G], s_pre[G + 1];
-  const int first = blockIdx.x * G;
-  if (first >= count) return;
   if (threadIdx.x < G) {
     const int i = first + (int)threadIdx.x;
     int pid = -1, code = 0, cnt = 0;
@@ -265,6 +278,24 @@ __global__ __launch_bounds__(NT) void k_fill_cf_coarse(DevMesh m, double* __rest
       }
     }
   }
+}
+
+// Block b takes the group of G regions starting at G b.  With `dir` (batched
+// launches) the list and count are read at run time.
+template <int D, int NT, int G>
+__global__ __launch_bounds__(NT) void k_fill_cf_coarse(DevMesh m,
+                                                       double* __restrict__ U,
+                                                       const int* __restrict__ list, int count,
+                                                       const int* __restrict__ dir,
+                                                       int* __restrict__ err) {
+  __shared__ int s_pid[G], s_code[G], s_pre[G + 1];
+  if (dir) {
+    list += dir[0];
+    count = dir[1];
+  }
+  const int first = (int)blockIdx.x * G;
+  if (first < count)
+    fill_cf_coarse_group<D, NT, G>(m, U, list, count, first, err, s_pid, s_code, s_pre);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,10 +535,15 @@ __device__ __forceinline__ void restrict_children(const DevMesh& m, double* __re
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict__ U,
-                                                  const int* __restrict__ list, int count) {
-  if ((int)blockIdx.x >= count) return;
-  restrict_patch<D>(m, U, list[blockIdx.x]);
+__global__ __launch_bounds__(256) void k_restrict(DevMesh m,
+                                                  double* __restrict__ U,
+                                                  const int* __restrict__ list, int count,
+                                                  const int* __restrict__ dir) {
+  if (dir) {
+    list += dir[0];
+    count = dir[1];
+  }
+  if ((int)blockIdx.x < count) restrict_patch<D>(m, U, list[blockIdx.x]);
 }
 
 // After a stage, in one launch: refluxing and the restriction of the two
@@ -522,14 +558,13 @@ __global__ __launch_bounds__(256) void k_restrict(DevMesh m, double* __restrict_
 // (block barrier between); the blocks touch disjoint cells otherwise:
 // refluxing changes leaf cells, restriction writes non-leaf cells.
 template <int D, int NT>
-__global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode, double* __restrict__ out,
-                                             const double* __restrict__ fr,
-                                             const int* __restrict__ rlist, int nref,
-                                             const int* __restrict__ plist, int npair,
-                                             const int* __restrict__ slist, int nsingle,
-                                             int lup, const double* __restrict__ dtp, double w,
-                                             unsigned long long* __restrict__ lam_next) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void post_block(const DevMesh& m, int mode, double* __restrict__ out,
+                                           const double* __restrict__ fr,
+                                           const int* __restrict__ rlist, int nref,
+                                           const int* __restrict__ plist, int npair,
+                                           const int* __restrict__ slist, int nsingle, int lup,
+                                           const double* __restrict__ dtp, double w,
+                                           unsigned long long* __restrict__ lam_next, int b) {
   if (b < nref) {
     reflux_item<D, NT>(m, mode, out, fr, rlist, b, dtp, w, lam_next);
     const int pid = rlist[2 * b];
@@ -547,6 +582,33 @@ __global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode, double* __rest
   } else if (b - nref - npair < nsingle) {
     restrict_patch<D>(m, out, slist[b - nref - npair]);
   }
+}
+
+
+// One block per block index.  With `dir` (batched launches) the three lists
+// and their counts are read at run time from their directory entries.
+template <int D, int NT>
+__global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode,
+                                             double* __restrict__ out,
+                                             const double* __restrict__ fr,
+                                             const int* __restrict__ rlist, int nref,
+                                             const int* __restrict__ plist, int npair,
+                                             const int* __restrict__ slist, int nsingle,
+                                             const int* __restrict__ dir,
+                                             int lup, const double* __restrict__ dtp, double w,
+                                             unsigned long long* __restrict__ lam_next) {
+  if (dir) {
+    // the three lists' directory entries, in order; rlist is the list buffer
+    const int* buf = rlist;
+    rlist = buf + dir[0];
+    nref = dir[1];
+    plist = buf + dir[2];
+    npair = dir[3];
+    slist = buf + dir[4];
+    nsingle = dir[5];
+  }
+  post_block<D, NT>(m, mode, out, fr, rlist, nref, plist, npair, slist, nsingle, lup, dtp, w,
+                    lam_next, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,11 +951,16 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
     else hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__);             \
   } while (0)
 
-void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, int* err,
-                      hipStream_t s) {
+void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, const int* dir,
+                      int* err, hipStream_t s) {
   if (count <= 0) return;
+  // one block per region (group of regions)
+  auto launch = [&](auto kern, int threads, int per_block) {
+    const int nb = (count + per_block - 1) / per_block;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, m, U, list, count, dir, err);
+  };
   switch (m.dim) {
-    case 1: k_fill_cf<1, 64><<<count, 64, 0, s>>>(m, U, list, count, err); break;
+    case 1: launch(k_fill_cf<1, 64>, 64, 1); break;
     case 2: {
       // refined patches of edge 16 or less: one fine cell per thread (a side
       // region is 4 n = 64 cells); wider ones: by coarse cell, two regions
@@ -905,9 +972,9 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
       int nmax = 0;
       for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
       if (nmax <= 16)
-        k_fill_cf<2, 64><<<count, 64, 0, s>>>(m, U, list, count, err);
+        launch(k_fill_cf<2, 64>, 64, 1);
       else
-        k_fill_cf_coarse<2, 64, 2><<<(count + 1) / 2, 64, 0, s>>>(m, U, list, count, err);
+        launch(k_fill_cf_coarse<2, 64, 2>, 64, 2);
       break;
     }
     default:
@@ -915,7 +982,7 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, i
       // patch covers 8, 16 or 32 coarse cells and one of a 16^3 patch 8 to
       // 128 (per launch on C5: 2.12 ms with 4 regions per block, 2.19 with
       // 8, 2.27 with 16)
-      k_fill_cf_coarse<3, 64, 4><<<(count + 3) / 4, 64, 0, s>>>(m, U, list, count, err);
+      launch(k_fill_cf_coarse<3, 64, 4>, 64, 4);
       break;
   }
 }
@@ -942,27 +1009,34 @@ void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
 
 void Kernels::post(const DevMesh& m, int mode, double* out, const double* fr,
                    const int* rlist, int nref, const int* plist, int npair, const int* slist,
-                   int nsingle, int lup, const double* dt, double w,
+                   int nsingle, const int* dir, int lup, const double* dt, double w,
                    unsigned long long* lam_next, hipStream_t s) {
   const int nb = nref + npair + nsingle;
   if (nb <= 0) return;
-#define AMR_POST(D, NT)                                                                     \
-  k_post<D, NT><<<nb, NT, 0, s>>>(m, mode, out, fr, rlist, nref, plist, npair, slist, nsingle, \
-                                  lup, dt, w, lam_next)
+  auto launch = [&](auto kern, int threads) {
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, m, mode, out, fr, rlist, nref,
+                       plist, npair, slist, nsingle, dir, lup, dt, w, lam_next);
+  };
   switch (m.dim) {
-    case 1: AMR_POST(1, 64); break;
-    case 2: AMR_POST(2, 256); break;
-    default: AMR_POST(3, 256); break;
+    case 1: launch(k_post<1, 64>, 64); break;
+    case 2: launch(k_post<2, 256>, 256); break;
+    default: launch(k_post<3, 256>, 256); break;
   }
-#undef AMR_POST
 }
 
 void Kernels::restrict_level(const DevMesh& m, double* U, const int* list, int count,
-                             hipStream_t s) {
+                             const int* dir, hipStream_t s) {
   if (count <= 0) return;
   // one block per child patch, one thread per covered parent cell
-  const int nt = m.dim == 3 ? 256 : 64;
-  AMR_DISPATCH_DIM(m.dim, k_restrict, dim3(count), dim3(nt), s, m, U, list, count);
+  auto launch = [&](auto kern, int threads) {
+    const int nb = count;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, m, U, list, count, dir);
+  };
+  switch (m.dim) {
+    case 1: launch(k_restrict<1>, 64); break;
+    case 2: launch(k_restrict<2>, 64); break;
+    default: launch(k_restrict<3>, 256); break;
+  }
 }
 
 void Kernels::max_rate(const DevMesh& m, const double* U, const int* list, int count,

@@ -713,27 +713,23 @@ __device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict_
   cells_at<D, TX, TY, 1, NT, 1>(sFy, frp, n, o, acc, inv_h, wmask);
 }
 
+// One (pid, tile) work item: the whole RHS of the tile and its stage
+// combination; `best` collects the CFL rate bits of the item's cells.
 template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH, bool CHAR>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (D <= 2 ? 6 : 7)))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
-                                              const double* Un, double* out,
-                                              double* __restrict__ fr,
-                                              const int* __restrict__ tiles, int count,
-                                              const double* __restrict__ dtp,
-                                              unsigned long long* __restrict__ lam_next,
-                                              const uint8_t* __restrict__ cfmask,
-                                              const unsigned long long* __restrict__ lam_in,
-                                              double* __restrict__ dt_out) {
+__device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
+                                           const double* __restrict__ Uin, const double* Un,
+                                           double* out, double* __restrict__ fr,
+                                           const int* __restrict__ tiles, int item,
+                                           const double* __restrict__ dtp,
+                                           unsigned long long* __restrict__ lam_next,
+                                           const uint8_t* __restrict__ cfmask,
+                                           const unsigned long long* __restrict__ lam_in,
+                                           double* __restrict__ dt_out, double* sP, double* sF,
+                                           long long* sN, unsigned long long& best) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int CPT = (S::NCELL + NT - 1) / NT;
   constexpr bool UNION = D <= 2;
-  constexpr int NU = S::NUNION;
-  // edge fluxes: one direction at a time, or x and y together (BOTH)
-  constexpr int NEDXY = (S::T0 + 3) * S::T1 + S::T0 * (S::T1 + 3);
-  __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
-  __shared__ double sF[(D + 2) * (BOTH ? NEDXY : S::EDMAX)];
-  const int item = xcd_item(count);
-  if (item >= count) return;
   const int pid = tiles[2 * item];
   const int tix = tiles[2 * item + 1];
   const int l = m.level[pid];
@@ -753,7 +749,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
-  __shared__ long long sN[27];
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
@@ -811,7 +806,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (
   // faces are left to the flux-correction kernel, which changes them
   const bool want_rate = lam_next != nullptr && mode == kModeStage3;
   const int fmask = want_rate ? cfmask[pid] : 0;
-  unsigned long long best = 0ull;
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int cell = threadIdx.x + cc * NT;
@@ -847,7 +841,43 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (
       }
     }
   }
-  if (want_rate) block_max_atomic(best, lam_next);
+}
+
+// The fused stage kernel over (pid, tile) work items, one item per block.
+// With `dir` (batched launches) the list and its live count are read from
+// the device list directory {offset into `tiles`, count}, so that a launch
+// recorded once stays valid when a regrid rewrites the lists (its grid may
+// then hold more blocks than items).  XCD x (block b runs on XCD b mod 8)
+// takes one contiguous eighth of the list, which is in brick order, so the
+// items in flight on an XCD are neighbours that read each other's cells as
+// halos from that XCD's L2.
+template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH, bool CHAR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (D <= 2 ? 6 : 7)))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+                                              const double* Un, double* out,
+                                              double* __restrict__ fr,
+                                              const int* __restrict__ tiles, int count,
+                                              const int* __restrict__ dir,
+                                              const double* __restrict__ dtp,
+                                              unsigned long long* __restrict__ lam_next,
+                                              const uint8_t* __restrict__ cfmask,
+                                              const unsigned long long* __restrict__ lam_in,
+                                              double* __restrict__ dt_out) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr bool UNION = D <= 2;
+  constexpr int NU = S::NUNION;
+  // edge fluxes: one direction at a time, or x and y together (BOTH)
+  constexpr int NEDXY = (S::T0 + 3) * S::T1 + S::T0 * (S::T1 + 3);
+  __shared__ double sP[(D + 2) * (UNION ? NU : S::EXTMAX)];
+  __shared__ double sF[(D + 2) * (BOTH ? NEDXY : S::EDMAX)];
+  __shared__ long long sN[27];
+  const int* list = dir ? tiles + dir[0] : tiles;
+  const int item = xcd_item(dir ? dir[1] : count);
+  if (item < 0) return;
+  unsigned long long best = 0ull;
+  stage_item<D, TX, TY, TZ, NT, FUSE, BOTH, CHAR>(m, mode, Uin, Un, out, fr, list, item, dtp,
+                                                  lam_next, cfmask, lam_in, dt_out, sP, sF, sN,
+                                                  best);
+  if (lam_next != nullptr && mode == kModeStage3) block_max_atomic(best, lam_next);
 }
 
 }  // namespace
@@ -890,25 +920,24 @@ int Kernels::tiles_per_patch(int v, int n) {
 }
 
 void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
-                    double* out, double* fr, const int* tiles, int count, const double* dt,
-                    bool fuse, unsigned long long* lam_next, const uint8_t* cfmask,
-                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                    double* out, double* fr, const int* tiles, int count, const int* dir,
+                    const double* dt, bool fuse, unsigned long long* lam_next,
+                    const uint8_t* cfmask, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
                     const unsigned long long* lam_in, double* dt_out) {
   if (count <= 0) return;
-  // one block per work item, rounded up to whole groups of kXcds blocks (see
-  // xcd_item)
+  // one block per work item (`count` may exceed the live count read from the
+  // directory), in whole groups of kXcds blocks (see xcd_item)
   const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
   const bool chr = m.scheme == AMR_SCHEME_CHAR;
 #define AMR_STAGE_K(D, TX, TY, TZ, NT, F, B, C)                                                \
   do {                                                                                          \
+    auto kern = k_stage<D, TX, TY, TZ, NT, F, B, C>;                                            \
     if (ev0)                                                                                    \
-      hipExtLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B, C>), dim3(nb), dim3(NT), 0, s,     \
-                            ev0, ev1, 0, m, mode, Uin, Un, out, fr, tiles, count, dt, lam_next, \
-                            cfmask, lam_in, dt_out);                                            \
+      hipExtLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, ev0, ev1, 0, m, mode, Uin, Un,  \
+                            out, fr, tiles, count, dir, dt, lam_next, cfmask, lam_in, dt_out);  \
     else                                                                                        \
-      hipLaunchKernelGGL((k_stage<D, TX, TY, TZ, NT, F, B, C>), dim3(nb), dim3(NT), 0, s, m,     \
-                         mode, Uin, Un, out, fr, tiles, count, dt, lam_next, cfmask, lam_in,    \
-                         dt_out);                                                               \
+      hipLaunchKernelGGL(kern, dim3(nb), dim3(NT), 0, s, m, mode, Uin, Un, out, fr, tiles, \
+                         count, dir, dt, lam_next, cfmask, lam_in, dt_out);                     \
   } while (0)
 #define AMR_STAGE_F(D, TX, TY, TZ, NT, F, B)          \
   do {                                                \

@@ -208,6 +208,7 @@ class RunStats:
     fallbacks: int
     uncovered_steps: int
     cell_updates: int
+    capacity_retries: int = 0   # learned regrids whose refinement did not fit the pools
 
     @property
     def wall_per_tsim(self) -> float:
@@ -257,7 +258,8 @@ def cover(h: A.Hierarchy, max_rounds: int) -> int:
 
 def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                pred: Optional[A.Predictor] = None, tau: float = 0.5,
-               judge: bool = False, rounds: int = 1, regrid_buffer: Optional[int] = None) -> RunStats:
+               judge: bool = False, rounds: int = 1, regrid_buffer: Optional[int] = None,
+               capacity_retries: int = 3) -> RunStats:
     """Advance `steps` steps under a regrid policy; wall time includes
     tagging, prediction, judging and regridding.
 
@@ -273,7 +275,7 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
     torch = A._torch()
     dt = torch.zeros(1, dtype=torch.float64, device=h.device)
     tsim = torch.zeros(1, dtype=torch.float64, device=h.device)
-    regrids = fallbacks = uncovered = cells = 0
+    regrids = fallbacks = uncovered = cells = capacity = 0
     own_buffer = h.cfg.tag_buffer
     max_rounds = h.cfg.max_levels - 1
     torch.cuda.synchronize()
@@ -289,13 +291,21 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
             if policy == "plain":
                 h.adapt()
             else:
-                try:
-                    learned_regrid(h, pred, tau, rounds)
-                except A.AMRError as e:
-                    # the predicted refinement does not fit the patch pools
-                    # (the regrid left the mesh unchanged): plain regrid
-                    if e.status != A.E_CAPACITY:
-                        raise
+                # a predicted refinement that does not fit the patch pools
+                # leaves the mesh unchanged (the regrid is transactional):
+                # retry with a stricter threshold (1 - tau halved), then
+                # fall back to a plain regrid
+                t = tau
+                for attempt in range(capacity_retries + 1):
+                    try:
+                        learned_regrid(h, pred, t, rounds)
+                        break
+                    except A.AMRError as e:
+                        if e.status != A.E_CAPACITY:
+                            raise
+                        capacity += 1
+                        t = 0.5 * (1.0 + t)
+                else:
                     h.adapt()
                     fallbacks += 1
             if regrid_buffer is not None:
@@ -308,4 +318,5 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                 uncovered += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells)
+    return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells,
+                    capacity)

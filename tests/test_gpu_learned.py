@@ -4,8 +4,9 @@ solver generates (single-level runs at the resolutions of the hierarchy's
 levels, labels = the plain tags of the next 16 steps), then the same seeded
 4-level run advances 128 steps under three regrid policies, each under the
 plain-tag judge with fallback (after every step the plain tagger checks that
-every tagged cell lies in a finest-level leaf, and a plain regrid follows at
-once when one does not):
+every tagged cell lies in a finest-level leaf, and plain regrids follow at
+once until it does, so every policy runs at full coverage of the plain
+tags):
 
   plain every 2 steps, plain every 16 steps, learned every 16 steps.
 
@@ -74,6 +75,10 @@ def test_learned_regridding_gain(setup):
     # the three runs cover the same physical time (global dt from the same
     # physics to round-off; meshes differ only where refinement differs)
     assert abs(l16.t_sim - p2.t_sim) <= 0.02 * p2.t_sim
+    # identical (full) plain-tag coverage: after every step the judge's
+    # plain regrids leave no tagged cell outside the finest leaves
+    for r in runs.values():
+        assert r.uncovered_steps == 0 and r.as_dict()["coverage"] == 1.0, r.as_dict()
     # forecasting: fewer judge failures than plain regridding at the same
     # interval
     assert l16.fallbacks < p16.fallbacks, (l16.as_dict(), p16.as_dict())

@@ -72,6 +72,10 @@ def test_learned_regridding_gain_3d(setup):
         print(name, runs[name].as_dict())
     p2, p16, l16 = runs["plain2"], runs["plain16"], runs["learned16"]
     assert abs(l16.t_sim - p2.t_sim) <= 0.02 * p2.t_sim
+    # identical (full) plain-tag coverage: after every step the judge's
+    # plain regrids leave no tagged cell outside the finest leaves
+    for r in runs.values():
+        assert r.uncovered_steps == 0 and r.as_dict()["coverage"] == 1.0, r.as_dict()
     # forecasting: at most half the judge failures of plain regridding at the
     # same interval
     assert l16.fallbacks <= 0.5 * p16.fallbacks, (l16.as_dict(), p16.as_dict())
