@@ -221,18 +221,19 @@ def copy_calibration(gib: int = 1) -> int:
 
 
 def train_predictor(dim: int, horizon: int, buffer: int, runs: int, epochs: int,
-                    recall: float, seed_eval: int, base: int, n: int = None):
+                    recall: float, seed_eval: int, base: int, n: int = None, res=None):
     """Train the refinement predictor on the solver's own tags: single-level
     periodic runs of the workload's generator (2D quadrants + blobs on 16^2
-    patches, 3D blasts + perturbations on 8^3 tiles) at resolutions base and
-    2 base, labels = the plain tagger's dilated tags over the next
-    ``horizon`` steps.  Returns the trained weights and what the comparison
-    needs (normalisation, tau for ``recall`` of the held-out patches)."""
+    patches, 3D blasts + perturbations on 8^3 tiles) at resolutions ``res``
+    (default base and 2 base), seeds 4000 + k (2D) or 5000 + k (3D), labels
+    = the plain tagger's dilated tags over the next ``horizon`` steps.
+    Returns the trained weights and what the comparison needs
+    (normalisation, tau for ``recall`` of the held-out patches)."""
     from paper_2508_05020_amd import amr, learned, workloads
     if n is None:
         n = 16 if dim == 2 else 8
     seeds = list(range(4000 if dim == 2 else 5000, (4000 if dim == 2 else 5000) + runs))
-    res = (base, 2 * base)
+    res = tuple(res) if res else (base, 2 * base)
     t0 = time.perf_counter()
     mean, std = learned.input_statistics(
         [learned.uniform_config(base, n, tag_buffer=buffer, dim=dim)], seeds[:1], steps=8)
@@ -338,8 +339,8 @@ def learned_gain(args) -> int:
                 ("B_plain2", 2, "plain", amr.EXEC_BATCHED, None),
                 (f"B{H}_plain{H}_dilation{wide}", H, "plain", amr.EXEC_BATCHED, wide),
                 (f"BL_learned{H}", H, "learned", amr.EXEC_BATCHED, None)]
-    if args.learned_eval:
-        policies = policies[1:]  # one launch per patch and phase: hours on a large workload
+    if args.learned_eval and dim == 3:
+        policies = policies[1:]  # one launch per patch and phase: hours on a 3D workload
     results = compare_policies(ecfg, eseed, args.steps, policies, trained, rounds)
     L = results[f"BL_learned{H}"]["wall_per_tsim"]
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
@@ -370,8 +371,9 @@ def learned_vs_plain(cfg, args):
         return None  # the 2D network predicts leaves of one patch edge
     trained = train_predictor(cfg.dim, H, cfg.tag_buffer, args.train_runs, args.epochs,
                               args.recall, 5100 if cfg.dim == 3 else 4100,
-                              base=32 if cfg.dim == 3 else 128,
-                              n=8 if cfg.dim == 3 else cfg.patch_cells[0])
+                              base=64 if cfg.dim == 3 else 128,
+                              n=8 if cfg.dim == 3 else cfg.patch_cells[0],
+                              res=(64,) if cfg.dim == 3 else None)
     wide = min(3, math.ceil(H * cfg.cfl))
     policies = [("B_plain2", 2, "plain", amr.EXEC_BATCHED, None),
                 (f"B{H}_plain{H}_dilation{wide}", H, "plain", amr.EXEC_BATCHED, wide),
