@@ -291,7 +291,7 @@ def compare_policies(ecfg, eseed: int, steps: int, policies, trained, rounds: in
         torch.cuda.synchronize()
         log(f"[learned] {name}: initial hierarchy in {time.perf_counter() - t0:.1f} s")
         st = learned.run_policy(h, steps, every, kind, pred, trained["tau"] if pred else 0.5,
-                                judge=True, rounds=rounds, regrid_buffer=buf)
+                                judge=True, rounds=rounds, regrid_buffer=buf, progress=8)
         results[name] = st.as_dict()
         log(f"[learned] {name}: {results[name]}")
         if pred is not None:

@@ -79,7 +79,7 @@ typedef struct {
   double lo, hi;                     /* domain [lo, hi)^dim */
   double gamma;                      /* ratio of specific heats (1.4) */
   double cfl;                        /* dt = cfl / max_leaf sum_j (|u_j| + c) / h_l */
-  double weno_eps;                   /* WENO5-JS epsilon (1e-6) */
+  double weno_eps;                   /* WENO5-JS epsilon (1e-6), in [1e-20, 1] */
   double tag_theta;                  /* gradient tag threshold (0.02) */
   int tag_buffer;                    /* tag dilation in cells (0 .. 3) */
   int max_patches;                   /* total patch slots over all levels */

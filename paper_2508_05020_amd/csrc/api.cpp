@@ -245,6 +245,9 @@ void validate_config(const amr_config& c) {
   if (!(c.hi > c.lo)) throw ArgError("empty domain");
   if (!(c.gamma > 1.0)) throw ArgError("gamma must exceed 1");
   if (!(c.cfl > 0.0)) throw ArgError("cfl must be positive");
+  // the stage kernel forms 1/(den_L den_R) of the two WENO sides at an edge,
+  // products of (eps + beta)^2 terms that must stay normal numbers
+  if (!(c.weno_eps >= 1e-20 && c.weno_eps <= 1.0)) throw ArgError("weno_eps must be in [1e-20, 1]");
   if (c.tag_buffer < 0 || c.tag_buffer > 3) throw ArgError("tag_buffer must be in 0..3");
   if (c.scheme != AMR_SCHEME_WENO && c.scheme != AMR_SCHEME_CENTRAL && c.scheme != AMR_SCHEME_CHAR)
     throw ArgError("scheme must be AMR_SCHEME_WENO, _CENTRAL or _CHAR");

@@ -71,56 +71,64 @@ __device__ __forceinline__ void sqrt_rsqrt_nr(double x, double& s, double& is) {
   is = 2.0 * h;
 }
 
-// Nonlinear WENO5-JS combination of three candidates from their smoothness
-// indicators.  The weights alpha_k / sum(alpha) with alpha_k = d_k / t_k,
-// t_k = (eps + beta_k)^2 and d = (1, 10, 5)/16 are evaluated as cross
-// products, so one division serves all three.  Inputs are scaled: candidates
-// by 8, indicators and eps by 4; with power-of-two factors the scaling is
-// exact and only the final 1/8 is applied.
-__device__ __forceinline__ double weno_combine(double b0, double b1, double b2, double q0,
-                                               double q1, double q2, double eps4) {
+// Numerator and denominator of the nonlinear WENO5-JS combination of three
+// candidates q_k from their smoothness indicators b_k: the value is
+// sum(alpha_k q_k) / sum(alpha_k) with alpha_k = d_k / t_k, t_k = (eps +
+// b_k)^2 and d = (1, 10, 5)/16, evaluated as cross products (alpha_k times
+// t0 t1 t2 / 16): num = t2 (t1 q0 + 10 t0 q1) + 5 t0 t1 q2, den = t2 (t1 +
+// 10 t0) + 5 t0 t1.
+__device__ __forceinline__ void weno_num_den(double b0, double b1, double b2, double q0, double q1,
+                                             double q2, double eps4, double& num, double& den) {
   const double e0 = eps4 + b0, e1 = eps4 + b1, e2 = eps4 + b2;
   const double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
-  const double a0 = t1 * t2;
-  const double a1 = 10.0 * (t0 * t2);
-  const double a2 = 5.0 * (t0 * t1);
-  const double num = fma(a2, q2, fma(a1, q1, a0 * q0));
-  return (num * rcp_nr((a0 + a1) + a2)) * 0.125;
+  const double c0 = 10.0 * t0;
+  const double p5 = 5.0 * (t0 * t1);
+  den = fma(t2, c0 + t1, p5);
+  num = fma(t2, fma(c0, q1, t1 * q0), p5 * q2);
 }
 
 // WENO5-JS point values on both sides of the edge between v2 and v3 from the
 // six nodes v0..v5: the left-biased value from v0..v4 and the right-biased
 // value from the mirrored stencil v5..v1.  Candidates: the quadratic through
 // three consecutive nodes evaluated at the edge (x8), two of which the sides
-// share; indicators (x4): 13/12 (second difference)^2 + 1/4 (first-difference
-// form)^2 of the Jiang-Shu definition, with the second differences of the
-// two middle windows shared.
+// share.  Indicators (x4): 13/12 k^2 + 1/4 s^2 of the Jiang-Shu definition
+// for the window (a, b, c), with k = a - 2b + c and s the first-derivative
+// form at the node the edge adjoins: a - 4b + 3c (window left of the edge),
+// a - c (centred), 3a - 4b + c (window right of it).  With the first
+// differences d_i = v_(i+1) - v_i, k_w = d_(w+1) - d_w and the three forms
+// are k + 2 d_(w+1), -(d_w + d_(w+1)) and k - 2 d_w, so the four windows
+// share their differences.  One reciprocal serves both sides: 1/(den_L
+// den_R) (the indicators are bounded below by eps, and eps is at least
+// 1e-20, so the product stays a normal number) times the other side's
+// denominator, and with it the final 1/8.  The scalings are powers of two.
 __device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
                                            double v5, double eps4, double& L, double& R) {
   const double qa = fma(15.0, v2, fma(-10.0, v1, 3.0 * v0));  // left, nodes v0..v2
   const double qb = fma(3.0, v3, fma(6.0, v2, -v1));          // nodes v1..v3 (both sides)
   const double qc = fma(6.0, v3, fma(3.0, v2, -v4));          // nodes v2..v4 (both sides)
   const double qd = fma(15.0, v3, fma(-10.0, v4, 3.0 * v5));  // right, nodes v3..v5
-  const double k0 = fma(-2.0, v1, v0) + v2;
-  const double k1 = fma(-2.0, v2, v1) + v3;
-  const double k2 = fma(-2.0, v3, v2) + v4;
-  const double k3 = fma(-2.0, v4, v3) + v5;
+  const double d0 = v1 - v0, d1 = v2 - v1, d2 = v3 - v2, d3 = v4 - v3, d4 = v5 - v4;
+  const double k0 = d1 - d0, k1 = d2 - d1, k2 = d3 - d2, k3 = d4 - d3;
   constexpr double c4 = 4.0 * (13.0 / 12.0);
   const double g0 = c4 * k0, g1 = c4 * k1, g2 = c4 * k2, g3 = c4 * k3;
-  const double sl0 = fma(3.0, v2, fma(-4.0, v1, v0));
-  const double sl1 = v1 - v3;
-  const double sl2 = fma(3.0, v2, fma(-4.0, v3, v4));
-  const double sr0 = fma(3.0, v3, fma(-4.0, v4, v5));
-  const double sr1 = v4 - v2;
-  const double sr2 = fma(3.0, v3, fma(-4.0, v2, v1));
+  const double sl0 = fma(2.0, d1, k0);   // window v0..v2, node v2
+  const double sl1 = d1 + d2;            // window v1..v3, centred
+  const double sl2 = fma(-2.0, d2, k2);  // window v2..v4, node v2
+  const double sr0 = fma(-2.0, d3, k3);  // window v3..v5, node v3
+  const double sr1 = d2 + d3;            // window v2..v4, centred
+  const double sr2 = fma(2.0, d2, k1);   // window v1..v3, node v3
   const double bl0 = fma(g0, k0, sl0 * sl0);
   const double bl1 = fma(g1, k1, sl1 * sl1);
   const double bl2 = fma(g2, k2, sl2 * sl2);
   const double br0 = fma(g3, k3, sr0 * sr0);
   const double br1 = fma(g2, k2, sr1 * sr1);
   const double br2 = fma(g1, k1, sr2 * sr2);
-  L = weno_combine(bl0, bl1, bl2, qa, qb, qc, eps4);
-  R = weno_combine(br0, br1, br2, qd, qc, qb, eps4);
+  double nl, dl, nr, dr;
+  weno_num_den(bl0, bl1, bl2, qa, qb, qc, eps4, nl, dl);
+  weno_num_den(br0, br1, br2, qd, qc, qb, eps4, nr, dr);
+  const double inv = rcp_nr(dl * dr) * 0.125;
+  L = nl * (dr * inv);
+  R = nr * (dl * inv);
 }
 
 __device__ __forceinline__ double central4(double b, double c, double d, double e) {
@@ -605,10 +613,16 @@ __device__ __forceinline__ void edges_dir(const DevMesh& m, const double* sP, do
   constexpr int G2 = S::T2 + (J == 2 ? 3 : 0);
   constexpr int NED = G0 * G1 * G2;
   constexpr int STEP = J == 0 ? 1 : (J == 1 ? E0 : E0 * E1);
-  for (int e = threadIdx.x; e < NED; e += NT) {
-    const int a0 = e % G0;
-    const int a1 = (e / G0) % G1;
-    const int a2 = e / (G0 * G1);
+  for (int t = threadIdx.x; t < NED; t += NT) {
+    // 3D x edges go to the lanes cross-section first: the 16 lanes of an LDS
+    // pass then read rows r..r+15 of the odd-pitched node box and write
+    // edges a0 + 11 r (distinct banks); row by row, 11 edges to a row, they
+    // would collide
+    constexpr bool XCROSS = !UNION && J == 0;
+    const int a0 = XCROSS ? t / (G1 * G2) : t % G0;
+    const int a1 = XCROSS ? t % G1 : (t / G0) % G1;
+    const int a2 = XCROSS ? (t / G1) % G2 : t / (G0 * G1);
+    const int e = XCROSS ? a0 + G0 * (a1 + G1 * a2) : t;
     // layout index of node i-2 of this edge's window
     int base;
     if constexpr (!UNION) base = a0 + E0 * (a1 + E1 * a2);

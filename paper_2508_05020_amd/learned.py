@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 import time
 from typing import Dict, List, Optional, Sequence
 
@@ -259,7 +260,7 @@ def cover(h: A.Hierarchy, max_rounds: int) -> int:
 def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                pred: Optional[A.Predictor] = None, tau: float = 0.5,
                judge: bool = False, rounds: int = 1, regrid_buffer: Optional[int] = None,
-               capacity_retries: int = 3) -> RunStats:
+               capacity_retries: int = 3, progress: int = 0) -> RunStats:
     """Advance `steps` steps under a regrid policy; wall time includes
     tagging, prediction, judging and regridding.
 
@@ -316,6 +317,9 @@ def run_policy(h: A.Hierarchy, steps: int, every: int, policy: str = "plain",
                 fallbacks += 1
             if made < 0:
                 uncovered += 1
+        if progress and s % progress == 0:
+            print(f"[policy] {policy}: step {s}/{steps}, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return RunStats(policy, steps, wall, float(tsim.item()), regrids, fallbacks, uncovered, cells,
