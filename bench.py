@@ -319,7 +319,7 @@ def learned_gain(args) -> int:
             raise SystemExit("the 2D network needs one patch edge on every level")
         n = edges.pop()
     trained = train_predictor(dim, H, b, args.train_runs, args.epochs, args.recall, seed_eval,
-                              base=64 if dim == 2 else 32, n=n)
+                              base=64 if dim == 2 else 32, n=n, res=args.train_res)
     if args.learned_eval:
         ecfg = workloads.config(args.learned_eval).replace(tag_buffer=b)
         if ecfg.dim != dim:
@@ -474,6 +474,9 @@ def main() -> int:
                     help="seed of the evaluation run (default 4100 in 2D, 5100 in 3D)")
     ap.add_argument("--train-runs", type=int, default=16,
                     help="seeded single-level runs the predictor is trained on")
+    ap.add_argument("--train-res", type=int, nargs="+", default=None,
+                    help="resolutions of the single-level training runs (default: the "
+                         "training base and twice it)")
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--recall", type=float, default=0.995,
                     help="fraction of held-out patches with a future tag the mask must flag")

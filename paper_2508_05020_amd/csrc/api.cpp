@@ -255,6 +255,9 @@ void validate_config(const amr_config& c) {
   for (int l = 0; l < c.max_levels; ++l) {
     const int n = c.patch_cells[l];
     if (n < 4 || n % 2) throw ArgError("patch edge must be even and >= 4");
+    // in-patch offsets are 32-bit, formed with 24-bit multiplies
+    if (n > (c.dim == 3 ? 1024 : (c.dim == 2 ? 16384 : (1 << 22))))
+      throw ArgError("patch edge too large (3D 1024, 2D 16384)");
     if (((long long)c.base_cells << l) % n) throw ArgError("level cells not divisible by patch");
     if (l + 1 < c.max_levels && (2 * n) % c.patch_cells[l + 1])
       throw ArgError("fine patch edge must divide twice the coarse edge");

@@ -28,17 +28,19 @@ __device__ __forceinline__ int bc_map(int g, int N, int periodic) {
 }
 
 template <int D>
-__device__ __forceinline__ long long box_off(int full, int x, int y, int z) {
+__device__ __forceinline__ int box_off(int full, int x, int y, int z) {
+  // offsets inside one patch fit 32 bits, and the factors 24 (one full-rate
+  // 24-bit multiply-add each instead of 64-bit products)
   if constexpr (D == 1) return x;
-  if constexpr (D == 2) return (long long)y * full + x;
-  return ((long long)z * full + y) * full + x;
+  if constexpr (D == 2) return __mul24(y, full) + x;
+  return __mul24(__mul24(z, full) + y, full) + x;
 }
 
 template <int D>
-__device__ __forceinline__ long long var_stride(int full) {
+__device__ __forceinline__ int var_stride(int full) {
   if constexpr (D == 1) return full;
-  if constexpr (D == 2) return (long long)full * full;
-  return (long long)full * full * full;
+  if constexpr (D == 2) return __mul24(full, full);
+  return __mul24(__mul24(full, full), full);
 }
 
 __device__ __forceinline__ long long patch_base(const DevMesh& m, int pid, int l) {
@@ -67,8 +69,8 @@ __device__ bool fetch_cell(const DevMesh& m, const double* __restrict__ U, int l
   const int pid = map_at<D>(m, l, q);
   if (pid < 0) return false;
   const double* P = U + patch_base(m, pid, l);
-  const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
-  const long long vs = var_stride<D>(L.full);
+  const int off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+  const int vs = var_stride<D>(L.full);
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) out[v] = P[v * vs + off];
   return true;
@@ -105,7 +107,7 @@ __device__ bool prolong_cell(const DevMesh& m, const double* __restrict__ U, int
   // all map lookups first, then all loads, so the latencies overlap
   int pids[NS];
   long long offs[NS];
-  const long long vs = var_stride<D>(C.full);
+  const int vs = var_stride<D>(C.full);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     int gs[3] = {gc[0], gc[1], gc[2]};

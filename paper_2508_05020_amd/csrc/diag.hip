@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_velocity_gradient(DevMesh m, const doub
     const int l = m.level[pid];
     const LevelC& L = m.lv[l];
     const int n = L.n, f = L.full;
-    const long long vs = var_stride<D>(f);
+    const int vs = var_stride<D>(f);
     const double* P = U + patch_base(m, pid, l);
     // cell layout of one variable: the patch's box at its state offset / nvar
     double* O = out + (L.pool_off + (long long)(pid - L.pid_base) * L.stride) / m.nvar;

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_fill(DevMesh m, double* __restrict__ U,
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n, full = L.full;
-  const long long vs = var_stride<D>(full);
+  const int vs = var_stride<D>(full);
   double* P = U + patch_base(m, pid, l);
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
   const int total = (int)vs;
@@ -88,7 +88,7 @@ __device__ __forceinline__ void fill_cf_region(const DevMesh& m, double* __restr
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n, full = L.full;
-  const long long vs = var_stride<D>(full);
+  const int vs = var_stride<D>(full);
   double* P = U + patch_base(m, pid, l);
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
   int start[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
@@ -111,7 +111,7 @@ __device__ __forceinline__ void fill_cf_region(const DevMesh& m, double* __restr
       err[0] = 1;
       for (int v = 0; v < NV; ++v) val[v] = __builtin_nan("");
     }
-    const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
+    const int off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
 #pragma unroll
     for (int v = 0; v < NV; ++v) P[v * vs + off] = val[v];
   }
@@ -182,7 +182,7 @@ __device__ __forceinline__ void fill_cf_coarse_group(const DevMesh& m, double* _
     const int l = m.level[pid];
     const LevelC& L = m.lv[l];
     const int n = L.n, full = L.full;
-    const long long vs = var_stride<D>(full);
+    const int vs = var_stride<D>(full);
     double* P = U + patch_base(m, pid, l);
     int start[3] = {0, 0, 0}, half[3] = {1, 1, 1};
     for (int j = 0; j < D; ++j) {
@@ -228,7 +228,7 @@ __device__ __forceinline__ void fill_cf_coarse_group(const DevMesh& m, double* _
     if (!found) {
       err[0] = 1;
       for (int f = 0; f < NF; ++f) {
-        const long long off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
+        const int off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
                                          c0[2] + ((f >> 2) & 1) + NG);
 #pragma unroll
         for (int v = 0; v < NV; ++v) P[v * vs + off] = __builtin_nan("");
@@ -268,7 +268,7 @@ __device__ __forceinline__ void fill_cf_coarse_group(const DevMesh& m, double* _
       if (!(ch[0] > 0.0 && p > 0.0)) bad = true;
     }
     for (int f = 0; f < NF; ++f) {
-      const long long off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
+      const int off = box_off<D>(full, c0[0] + (f & 1) + NG, c0[1] + ((f >> 1) & 1) + NG,
                                        c0[2] + ((f >> 2) & 1) + NG);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -406,7 +406,7 @@ __device__ __forceinline__ void reflux_item(const DevMesh& m, int mode, double* 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
   const double* frc = fr + L.fr_off + (long long)(pid - L.pid_base) * L.fr_stride;
   double* P = out + patch_base(m, pid, l);
-  const long long vs = var_stride<D>(L.full);
+  const int vs = var_stride<D>(L.full);
   const double coef = (mode == kModeRHS) ? L.inv_h : (w * dtp[0]) * L.inv_h;
   const bool want_rate = lam_next != nullptr && mode == kModeStage3;
   auto on_face = [&](const int c[3], int g) {
@@ -432,7 +432,7 @@ __device__ __forceinline__ void reflux_item(const DevMesh& m, int mode, double* 
     for (int g = 0; g < f; ++g) owned &= !((mask & (1 << g)) && on_face(c, g));
     if (!owned) continue;
     // the cell's values stay in registers through all of its corrections
-    const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+    const int off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
     double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(256) void k_max_rate(DevMesh m, const double* __res
     const LevelC& L = m.lv[l];
     const int n = L.n;
     const double* P = U + patch_base(m, pid, l);
-    const long long vs = var_stride<D>(L.full);
+    const int vs = var_stride<D>(L.full);
     int total = n;
     if constexpr (D >= 2) total *= n;
     if constexpr (D >= 3) total *= n;
@@ -636,7 +636,7 @@ __global__ __launch_bounds__(256) void k_max_rate(DevMesh m, const double* __res
       const int x = idx % n;
       const int y = D >= 2 ? (idx / n) % n : 0;
       const int z = D >= 3 ? idx / (n * n) : 0;
-      const long long off = box_off<D>(L.full, x + NG, y + NG, z + NG);
+      const int off = box_off<D>(L.full, x + NG, y + NG, z + NG);
       double u[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(256) void k_tag(DevMesh m, const double* __restrict
   const LevelC& L = m.lv[l];
   const int n = L.n, b = m.tag_buffer, w = n + 2 * b;
   const double* P = U + patch_base(m, pid, l);
-  const long long vs = var_stride<D>(L.full);
+  const int vs = var_stride<D>(L.full);
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
   // same-level neighbours by offset code (o0+1) + 3 (o1+1) + 9 (o2+1)
   __shared__ int sN[27];
@@ -815,7 +815,7 @@ __global__ __launch_bounds__(256) void k_cell_tags(DevMesh m, const uint8_t* __r
   const int l = m.level[pid];
   const LevelC& L = m.lv[l];
   const int n = L.n, b = m.tag_buffer;
-  const long long vs = var_stride<D>(L.full);
+  const int vs = var_stride<D>(L.full);
   const uint8_t* rp = raw + L.tag_off + (long long)(pid - L.pid_base) * vs;
   uint8_t* op = out + L.tag_off + (long long)(pid - L.pid_base) * vs;
   int total = n;
@@ -874,7 +874,7 @@ __global__ __launch_bounds__(256) void k_prolong_new(DevMesh m, double* __restri
   const LevelC& L = m.lv[l];
   const int n = L.n;
   double* P = U + patch_base(m, pid, l);
-  const long long vs = var_stride<D>(L.full);
+  const int vs = var_stride<D>(L.full);
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
   int total = n;
   if constexpr (D >= 2) total *= n;
@@ -890,7 +890,7 @@ __global__ __launch_bounds__(256) void k_prolong_new(DevMesh m, double* __restri
       err[0] = 1;
       for (int v = 0; v < NV; ++v) val[v] = __builtin_nan("");
     }
-    const long long off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
+    const int off = box_off<D>(L.full, c[0] + NG, c[1] + NG, c[2] + NG);
 #pragma unroll
     for (int v = 0; v < NV; ++v) P[v * vs + off] = val[v];
   }
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
   const LevelC& L = m.lv[l];
   const int n = L.n;
   const double* P = U + patch_base(m, pid, l);
-  const long long vs = var_stride<D>(L.full);
+  const int vs = var_stride<D>(L.full);
   int total = n;
   if constexpr (D >= 2) total *= n;
   if constexpr (D >= 3) total *= n;
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
     const int y = D >= 2 ? (idx / n) % n : 0;
     const int z = D >= 3 ? idx / (n * n) : 0;
     double u[NV];
-    const long long off = box_off<D>(L.full, x + NG, y + NG, z + NG);
+    const int off = box_off<D>(L.full, x + NG, y + NG, z + NG);
     for (int v = 0; v < NV; ++v) u[v] = P[v * vs + off];
     const double p = pressure_exact<D>(u, m.gm1);
     if (!(u[0] > 0.0 && p > 0.0)) ++cnt;

@@ -277,14 +277,14 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
   constexpr int NV = D + 2;
   bool inside = true;
   for (int j = 0; j < D; ++j) inside &= (c[j] >= 0 && c[j] < n);
-  const long long vs = var_stride<D>(full);
+  const int vs = var_stride<D>(full);
   if (FUSE && !inside) {
     const int np = m.lv[l].np;
     int code = 0, loc[3] = {0, 0, 0}, mul = 1;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       int o = c[j] < 0 ? -1 : (c[j] >= n ? 1 : 0);
-      int lj = c[j] - o * n;
+      int lj = o == 0 ? c[j] : (o < 0 ? c[j] + n : c[j] - n);
       if (o != 0 && !m.periodic[j] && (unsigned)(pc[j] + o) >= (unsigned)np) {
         o = 0;
         lj = c[j] < 0 ? 0 : n - 1;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
     const long long sb = sNB[code];
     if (sb >= 0) {
       const double* S = Uin + sb;
-      const long long off = box_off<D>(full, loc[0] + NG, loc[1] + NG, loc[2] + NG);
+      const int off = box_off<D>(full, loc[0] + NG, loc[1] + NG, loc[2] + NG);
 #pragma unroll
       for (int v = 0; v < NV; ++v) u[v] = S[v * vs + off];
       return;
@@ -304,7 +304,7 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
     // no same-level source: the prolonged ghost value was written into the
     // patch's own ghost layer by the coarse-ghost fill pass
   }
-  const long long off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
+  const int off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
 }
@@ -578,10 +578,11 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
     int tang = 0;
     if constexpr (D == 2) tang = (J == 0) ? (o[1] + t1) : (o[0] + t0);
     if constexpr (D == 3) {
-      if constexpr (J == 0) tang = (o[1] + t1) + n * (o[2] + t2);
-      else if constexpr (J == 1) tang = (o[0] + t0) + n * (o[2] + t2);
-      else tang = (o[0] + t0) + n * (o[1] + t1);
+      if constexpr (J == 0) tang = (o[1] + t1) + __mul24(n, o[2] + t2);
+      else if constexpr (J == 1) tang = (o[0] + t0) + __mul24(n, o[2] + t2);
+      else tang = (o[0] + t0) + __mul24(n, o[1] + t1);
     }
+    double Gps[NV], Gms[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       // edge fluxes are stored doubled (the Rusanov 1/2 is applied here, as
@@ -591,8 +592,20 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
       const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
       const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
       acc[cc][v] = fma(-(Gp - Gm), half_inv_h, acc[cc][v]);
-      if (i == 0 && lo_reg) frp[((J * 2 + 0) * NV + v) * nface + tang] = 0.5 * Gm;
-      if (i == n - 1 && hi_reg) frp[((J * 2 + 1) * NV + v) * nface + tang] = 0.5 * Gp;
+      Gps[v] = Gp;
+      Gms[v] = Gm;
+    }
+    // the flux registers of this face (variable v at v nface + tang of the
+    // face's block; 32-bit offsets, 24-bit products)
+    if (i == 0 && lo_reg) {
+      double* fb = frp + __mul24((J * 2 + 0) * NV, nface) + tang;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fb[__mul24(v, nface)] = 0.5 * Gms[v];
+    }
+    if (i == n - 1 && hi_reg) {
+      double* fb = frp + __mul24((J * 2 + 1) * NV, nface) + tang;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fb[__mul24(v, nface)] = 0.5 * Gps[v];
     }
   }
 }
@@ -799,7 +812,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     cells_at<D, TX, TY, TZ, NT, 2>(sF, frp, n, o, acc, L.inv_h, wmask);
   }
 
-  const long long vs = var_stride<D>(full);
+  const int vs = var_stride<D>(full);
   // stage 1 of a step may take dt = CFL / rate from the rate slot itself
   // (every block computes it; the first work item publishes it for the rest
   // of the step and clears the slot stage 3 accumulates into)

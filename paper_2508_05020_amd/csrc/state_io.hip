@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_set_prim(DevMesh m, double* __restrict_
     const int l = m.level[pid];
     const LevelC& L = m.lv[l];
     const int n = L.n, f = L.full;
-    const long long vs = var_stride<D>(f);
+    const int vs = var_stride<D>(f);
     double* P = U + patch_base(m, pid, l);
     const double* S = prim + src[b];
     int ncell = n;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_set_prim(DevMesh m, double* __restrict_
       const int x = c % n;
       const int y = D >= 2 ? (c / n) % n : 0;
       const int z = D >= 3 ? c / (n * n) : 0;
-      const long long off = box_off<D>(f, x + NG, y + NG, z + NG);
+      const int off = box_off<D>(f, x + NG, y + NG, z + NG);
       const double rho = S[c];
       double uu = 0.0;
 #pragma unroll
