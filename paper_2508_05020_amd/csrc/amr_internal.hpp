@@ -84,6 +84,8 @@ struct Kernels {
   // ev0/ev1 (optional): events stamped at the dispatch's own start and end.
   // lam_in (stage 1 only, optional): take dt = CFL / *lam_in instead of *dt,
   // write it to *dt_out and clear *lam_next (the slot stage 3 accumulates in)
+  // In the stage modes a tile of the finest level (nlev - 1 >= 1) also
+  // restricts its new values into its parent patch.
   static void stage(const DevMesh& m, int mode, const double* Uin, const double* Un,
                     double* out, double* fr, const int* tiles, int count, const int* dir,
                     const double* dt, bool fuse, unsigned long long* lam_next,
@@ -98,10 +100,11 @@ struct Kernels {
   // without coarse/fine faces (slist); lup = finest level - 1
   // dir (nullable): the directory entries of the three lists, in order;
   // with it the list pointers are the list buffer, the live counts are read
-  // at run time and nref + npair + nsingle only sizes the grid
+  // at run time and nref + npair + nsingle only sizes the grid.
+  // fine_done: the stage kernel has already restricted the finest level.
   static void post(const DevMesh& m, int mode, double* out, const double* fr, const int* rlist,
                    int nref, const int* plist, int npair, const int* slist, int nsingle,
-                   const int* dir, int lup, const double* dt, double w,
+                   const int* dir, int lup, bool fine_done, const double* dt, double w,
                    unsigned long long* lam_next, hipStream_t s);
   static void restrict_level(const DevMesh& m, double* U, const int* list, int count,
                              const int* dir, hipStream_t s);

@@ -704,7 +704,8 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
     const int lup = h->forest.nlev - 2;
     Kernels::post(h->dm, stage, h->U[d], h->fr, h->d_lists, grid_count(h, h->reflux), h->d_lists,
                   grid_count(h, h->post_pairs), h->d_lists, grid_count(h, h->post_singles),
-                  h->reflux.dir, lup, dt, w[stage], stage == 3 ? lam_next : nullptr, h->stream);
+                  h->reflux.dir, lup, true, dt, w[stage], stage == 3 ? lam_next : nullptr,
+                  h->stream);
     h->check_launch();
     for (int l = lup - 1; l >= 1; --l)
       over_list_dir(h, h->restr[l], 1, [&](const int* p, int c, const int* dir) {

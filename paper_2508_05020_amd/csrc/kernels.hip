@@ -563,7 +563,7 @@ __device__ __forceinline__ void post_block(const DevMesh& m, int mode, double* _
                                            const int* __restrict__ rlist, int nref,
                                            const int* __restrict__ plist, int npair,
                                            const int* __restrict__ slist, int nsingle, int lup,
-                                           const double* __restrict__ dtp, double w,
+                                           int fine_done, const double* __restrict__ dtp, double w,
                                            unsigned long long* __restrict__ lam_next, int b) {
   if (b < nref) {
     reflux_item<D, NT>(m, mode, out, fr, rlist, b, dtp, w, lam_next);
@@ -574,11 +574,13 @@ __device__ __forceinline__ void post_block(const DevMesh& m, int mode, double* _
     }
   } else if (b - nref < npair) {
     const int pid = plist[b - nref];
-    restrict_children<D>(m, out, pid);
-    if (lup >= 1) {
+    // the stage kernel has restricted the finest level (the children) itself
+    // unless the launch says otherwise
+    if (!fine_done) {
+      restrict_children<D>(m, out, pid);
       __syncthreads();
-      restrict_patch<D>(m, out, pid);
     }
+    if (lup >= 1) restrict_patch<D>(m, out, pid);
   } else if (b - nref - npair < nsingle) {
     restrict_patch<D>(m, out, slist[b - nref - npair]);
   }
@@ -595,7 +597,8 @@ __global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode,
                                              const int* __restrict__ plist, int npair,
                                              const int* __restrict__ slist, int nsingle,
                                              const int* __restrict__ dir,
-                                             int lup, const double* __restrict__ dtp, double w,
+                                             int lup, int fine_done,
+                                             const double* __restrict__ dtp, double w,
                                              unsigned long long* __restrict__ lam_next) {
   if (dir) {
     // the three lists' directory entries, in order; rlist is the list buffer
@@ -607,8 +610,8 @@ __global__ __launch_bounds__(NT) void k_post(DevMesh m, int mode,
     slist = buf + dir[4];
     nsingle = dir[5];
   }
-  post_block<D, NT>(m, mode, out, fr, rlist, nref, plist, npair, slist, nsingle, lup, dtp, w,
-                    lam_next, blockIdx.x);
+  post_block<D, NT>(m, mode, out, fr, rlist, nref, plist, npair, slist, nsingle, lup, fine_done,
+                    dtp, w, lam_next, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1009,13 +1012,14 @@ void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
 
 void Kernels::post(const DevMesh& m, int mode, double* out, const double* fr,
                    const int* rlist, int nref, const int* plist, int npair, const int* slist,
-                   int nsingle, const int* dir, int lup, const double* dt, double w,
-                   unsigned long long* lam_next, hipStream_t s) {
+                   int nsingle, const int* dir, int lup, bool fine_done, const double* dt,
+                   double w, unsigned long long* lam_next, hipStream_t s) {
   const int nb = nref + npair + nsingle;
   if (nb <= 0) return;
   auto launch = [&](auto kern, int threads) {
     hipLaunchKernelGGL(kern, dim3(nb), dim3(threads), 0, s, m, mode, out, fr, rlist, nref,
-                       plist, npair, slist, nsingle, dir, lup, dt, w, lam_next);
+                       plist, npair, slist, nsingle, dir, lup, fine_done ? 1 : 0, dt, w,
+                       lam_next);
   };
   switch (m.dim) {
     case 1: launch(k_post<1, 64>, 64); break;

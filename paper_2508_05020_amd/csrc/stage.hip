@@ -235,6 +235,20 @@ __device__ __forceinline__ void node_store(const DevMesh& m, const double* u, do
   }
 }
 
+// The same, keeping what was stored in `keep` as well.
+template <int D, bool CHAR>
+__device__ __forceinline__ void node_store_keep(const DevMesh& m, const double* u, double* sP,
+                                                int next, int idx, double* keep) {
+  if constexpr (CHAR) {
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) keep[v] = u[v];
+  } else {
+    node_primitives<D>(m, u, keep);
+  }
+#pragma unroll
+  for (int k = 0; k < D + 2; ++k) sP[k * next + idx] = keep[k];
+}
+
 // Same-level patches around the tile's patch, by offset code
 // (o0+1) + 3 (o1+1) + 9 (o2+1), o in {-1,0,1}^D (periodic wrap), as the
 // offsets of their data in the state buffer (-1 where no patch or outside a
@@ -650,12 +664,15 @@ __device__ __forceinline__ void edges_dir(const DevMesh& m, const double* sP, do
 // extended-box layout.  The tile's own nodes come first in the thread order
 // and the 8 halo layers after them, so that a wave holds nodes of one kind
 // (the tile's own nodes are read straight from the patch); every thread
-// issues the loads of all its nodes before converting any.
+// issues the loads of all its nodes before converting any.  Thread t < NCELL
+// holds tile node t in every direction: it converts it once (J = 0), keeps
+// the values in `keep` and stores them again for J = 1, 2 (primitive
+// schemes).
 template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool CHAR>
 __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restrict__ Uin,
                                          const double* __restrict__ Pin, int n, int full,
                                          const int o[3], const int pc[3], int l,
-                                         const long long* sN, double* sP) {
+                                         const long long* sN, double* sP, double* keep) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int E0 = S::xpitch(J);             // row pitch
@@ -667,6 +684,8 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
   constexpr int HL = NC / TJ;                  // nodes of one layer across J
   constexpr int CA = J == 0 ? S::T1 : S::T0;   // extent of the lower cross direction
   constexpr int NNODE = NC + 8 * HL;           // nodes of the extended box
+  // the characteristic scheme's kernel has no registers to spare for it
+  constexpr bool KEEP = !CHAR;
   constexpr int ITER = (NNODE + NT - 1) / NT;
   double u[ITER][NV];
   int lidx[ITER];
@@ -692,11 +711,24 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
     const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
     lidx[k] = (t[0] + (J == 0 ? 4 : 0)) + E0 * ((t[1] + (J == 1 ? 4 : 0)) +
                                                 E1 * (t[2] + (J == 2 ? 4 : 0)));
+    if (KEEP && J > 0 && idx < NC) continue;  // kept since direction x
     node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
   }
+  static_assert(NT >= NC, "the tile's own nodes are the first item of each thread");
 #pragma unroll
-  for (int k = 0; k < ITER; ++k)
-    if (lidx[k] >= 0) node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
+  for (int k = 0; k < ITER; ++k) {
+    if (lidx[k] < 0) continue;
+    if (KEEP && k == 0 && (int)threadIdx.x < NC) {
+      if constexpr (J == 0) {
+        node_store_keep<D, CHAR>(m, u[0], sP, NEXT, lidx[0], keep);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sP[v * NEXT + lidx[0]] = keep[v];
+      }
+    } else {
+      node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
+    }
+  }
 }
 
 // 1D/2D: edge fluxes and their divergence for direction J from the union
@@ -742,6 +774,49 @@ __device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict_
 
 // One (pid, tile) work item: the whole RHS of the tile and its stage
 // combination; `best` collects the CFL rate bits of the item's cells.
+// Restriction of a finest-level tile into its parent patch, from the new
+// values of its cells (sR: variable v of tile cell i at sR[v NCELL + i]):
+// each parent cell is the mean of its 2^D children, summed as the
+// post-stage restriction sums them (x pairs first, then y, then z).  The
+// finest level is never the coarse side of a coarse/fine face, so its values
+// are final once the stage kernel has written them.
+template <int D, int TX, int TY, int TZ, int NT>
+__device__ __forceinline__ void restrict_tile(const DevMesh& m, double* __restrict__ out, int pid,
+                                              int l, const int o[3], const double* sR) {
+  using S = TileShape<D, TX, TY, TZ>;
+  constexpr int NV = D + 2;
+  constexpr int NC = S::NCELL;
+  constexpr int H0 = S::T0 / 2, H1 = D >= 2 ? S::T1 / 2 : 1, H2 = D >= 3 ? S::T2 / 2 : 1;
+  constexpr int NP = H0 * H1 * H2;
+  static_assert(S::T0 % 2 == 0 && (D < 2 || S::T1 % 2 == 0) && (D < 3 || S::T2 % 2 == 0),
+                "tiles cover whole 2^D groups of children");
+  const int ppid = m.parent[pid];
+  const LevelC& C = m.lv[l - 1];
+  const int h = m.lv[l].n / 2;
+  double* Pp = out + patch_base(m, ppid, l - 1);
+  const int vsc = var_stride<D>(C.full);
+  for (int k = threadIdx.x; k < NP; k += NT) {
+    const int a = k % H0, b = (k / H0) % H1, c = k / (H0 * H1);
+    int q[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      q[j] = m.coord[3 * pid + j] * h - m.coord[3 * ppid + j] * C.n + o[j] / 2 + (j == 0 ? a : (j == 1 ? b : c)) + NG;
+    const int dst = box_off<D>(C.full, q[0], q[1], q[2]);
+    auto at = [&](int v, int x, int y, int z) {
+      return sR[v * NC + (2 * a + x) + S::T0 * ((2 * b + y) + S::T1 * (2 * c + z))];
+    };
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      auto xsum = [&](int y, int z) { return at(v, 0, y, z) + at(v, 1, y, z); };
+      double r;
+      if constexpr (D == 1) r = xsum(0, 0) * 0.5;
+      else if constexpr (D == 2) r = (xsum(0, 0) + xsum(1, 0)) * 0.25;
+      else r = ((xsum(0, 0) + xsum(1, 0)) + (xsum(0, 1) + xsum(1, 1))) * 0.125;
+      Pp[v * vsc + dst] = r;
+    }
+  }
+}
+
 template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH, bool CHAR>
 __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
                                            const double* __restrict__ Uin, const double* Un,
@@ -795,16 +870,20 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     // 3D, direction by direction: the next direction's nodes are loaded in
     // the phase that forms the previous direction's divergence (sP is free
     // once the edges are done, sF is read), two block barriers per direction
-    load_dir<D, TX, TY, TZ, NT, 0, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    double keep[NV];
+    load_dir<D, TX, TY, TZ, NT, 0, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
+                                                   keep);
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 0, false, CHAR>(m, sP, sF);
     __syncthreads();
-    load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
+                                                   keep);
     cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 1, false, CHAR>(m, sP, sF);
     __syncthreads();
-    load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
+                                                   keep);
     cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 2, false, CHAR>(m, sP, sF);
@@ -833,6 +912,13 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
   // faces are left to the flux-correction kernel, which changes them
   const bool want_rate = lam_next != nullptr && mode == kModeStage3;
   const int fmask = want_rate ? cfmask[pid] : 0;
+  // a tile of the finest level is restricted into its parent here, from the
+  // values it writes (staged in sF, free once every thread has read its
+  // edge fluxes)
+  const bool restrict_here = mode != kModeRHS && l == m.nlev - 1 && l >= 1;
+  static_assert(S::NCELL <= S::EDMAX, "the staged cell values fit sF");
+  double* sR = sF;
+  if (restrict_here) __syncthreads();
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int cell = threadIdx.x + cc * NT;
@@ -856,6 +942,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
         r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
       out[a] = r[v];
+      if (restrict_here) sR[v * S::NCELL + cell] = r[v];
     }
     if (want_rate) {
       const int c3[3] = {o[0] + t0, o[1] + t1, o[2] + t2};
@@ -868,6 +955,10 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
       }
     }
   }
+  if (restrict_here) {
+    __syncthreads();
+    restrict_tile<D, TX, TY, TZ, NT>(m, out, pid, l, o, sR);
+  }
 }
 
 // The fused stage kernel over (pid, tile) work items, one item per block.
@@ -879,7 +970,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
 // items in flight on an XCD are neighbours that read each other's cells as
 // halos from that XCD's L2.
 template <int D, int TX, int TY, int TZ, int NT, bool FUSE, bool BOTH, bool CHAR>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : (D <= 2 ? 6 : 7)))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(CHAR ? 4 : 6))) void k_stage(DevMesh m, int mode, const double* __restrict__ Uin,
                                               const double* Un, double* out,
                                               double* __restrict__ fr,
                                               const int* __restrict__ tiles, int count,
