@@ -40,8 +40,8 @@ struct StateError : std::runtime_error {
   } while (0)
 
 // entries of the device list directory
-enum { kDirCf = 0, kDirTiles = 1, kDirReflux = 2, kDirPairs = 3, kDirSingles = 4, kDirRestr = 5,
-       kDirEntries = kDirRestr + amr::kMaxLev };
+enum { kDirCf = 0, kDirTiles = 1, kDirReflux = 2, kDirPairs = 3, kDirSingles = 4, kDirCfFace = 5,
+       kDirRestr = 6, kDirEntries = kDirRestr + amr::kMaxLev };
 
 }  // namespace
 
@@ -116,7 +116,9 @@ struct amr_hierarchy {
 
   // host mirrors of the work lists
   std::vector<int> lists;
-  amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfregions{}, cands{};
+  // cffaces: the face regions of cfregions (all the stage kernel reads;
+  // the tagger's dilated box reads the edge and corner regions too)
+  amr::ListView all{}, leaves{}, tiles{}, reflux{}, cfregions{}, cffaces{}, cands{};
   // post-stage restriction of the two finest levels (see Kernels::post)
   amr::ListView post_pairs{}, post_singles{};
   amr::ListView restr[amr::kMaxLev]{}, fresh[amr::kMaxLev]{};
@@ -473,6 +475,16 @@ void sync_tables(amr_hierarchy* h, bool full) {
       for (const auto& part : parts) L.insert(L.end(), part.begin(), part.end());
     }
   }
+  // the face regions among them (one nonzero offset component)
+  const int cf1 = begin_list();
+  for (int i = c0; i < cf1; i += 2) {
+    const int code = L[i + 1];
+    const int nz = (code % 3 != 1) + ((code / 3) % 3 != 1) + ((code / 9) % 3 != 1);
+    if (nz == 1) {
+      L.push_back(L[i]);
+      L.push_back(code);
+    }
+  }
   // coarsening candidates: patches whose children are all leaves
   const int k0 = begin_list();
   for (int pid : order) {
@@ -557,7 +569,8 @@ void sync_tables(amr_hierarchy* h, bool full) {
   const int* dd = h->d_dir;
   h->all = {h->d_lists + a0, a1 - a0};
   h->leaves = {h->d_lists + a1, c0 - a1};
-  h->cfregions = {h->d_lists + c0, (k0 - c0) / 2, dd + 2 * kDirCf};
+  h->cfregions = {h->d_lists + c0, (cf1 - c0) / 2, dd + 2 * kDirCf};
+  h->cffaces = {h->d_lists + cf1, (k0 - cf1) / 2, dd + 2 * kDirCfFace};
   h->cands = {h->d_lists + k0, t0 - k0};
   h->tiles = {h->d_lists + t0, (r0 - t0) / 2, dd + 2 * kDirTiles};
   h->reflux = {h->d_lists + r0, nref, dd + 2 * kDirReflux};
@@ -577,6 +590,7 @@ void sync_tables(amr_hierarchy* h, bool full) {
       hd[2 * e + 1] = lv.count;
     };
     put(kDirCf, h->cfregions);
+    put(kDirCfFace, h->cffaces);
     put(kDirTiles, h->tiles);
     put(kDirReflux, h->reflux);
     put(kDirPairs, h->post_pairs);
@@ -660,10 +674,11 @@ void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_onl
 }
 
 // ghosts the stage kernel reads from memory: all of them, or with the fused
-// halo only the prolonged ones
+// halo only the prolonged ones of the face regions (its stencils are
+// one-directional; edge and corner regions are read by no stencil)
 void stage_fill(amr_hierarchy* h, int buf) {
   if (h->fuse_halo) {
-    over_list_dir(h, h->cfregions, 2, [&](const int* p, int c, const int* dir) {
+    over_list_dir(h, h->cffaces, 2, [&](const int* p, int c, const int* dir) {
       Kernels::fill_cf(h->dm, h->U[buf], p, c, dir, h->d_flags, h->stream);
     });
   } else {
@@ -919,10 +934,10 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
       tiles = std::max(tiles, t);
     }
     // all, leaves, coarsening candidates, reflux (2), post-stage pairs and
-    // singles, restriction, new patches: 9 per patch; ghost regions: 2 per
-    // region and patch; tiles: 2 per tile
+    // singles, restriction, new patches: 9 per patch; ghost regions and
+    // their faces: 2 per region and patch; tiles: 2 per tile
     const long long regions = ipow(3, cfg->dim) - 1;
-    h->lists_cap = 2 * tiles + (9 + 2 * regions) * mp + 64;
+    h->lists_cap = 2 * tiles + (9 + 2 * regions + 2 * 2 * cfg->dim) * mp + 64;
     h->d_lists = (int*)h->dev_alloc(h->lists_cap * sizeof(int));
     h->d_dir = (int*)h->dev_alloc(2 * kDirEntries * sizeof(int));
     HIP_OK(hipHostMalloc((void**)&h->h_dir, 2 * kDirEntries * sizeof(int), hipHostMallocDefault));
