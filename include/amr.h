@@ -165,17 +165,23 @@ amr_status amr_fill_ghosts(amr_hierarchy* h, int buf);
 
 /* L(U) of buffer `buf` on every leaf patch (async), including the
  * coarse/fine flux correction: Section 2.2 fluxes and Eq. (9) divergence.
- * Ghosts of `buf` are filled first.  rhs_dev has amr_state_doubles()
- * entries in the state-buffer layout; leaf interiors are written. */
+ * The ghost cells the stencils read are filled first (with the fused halo,
+ * the default, only the prolonged cells of the face ghost regions: the
+ * stencils are one-directional, so edge and corner ghost regions keep their
+ * previous contents; amr_fill_ghosts fills them all).  rhs_dev has
+ * amr_state_doubles() entries in the state-buffer layout; leaf interiors
+ * are written. */
 amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev);
 
 /* dt = cfl / max over leaf cells of buffer `buf` of sum_j (|u_j| + c) / h_l,
  * with c from Eq. (7); written to the device scalar *dt_dev (async). */
 amr_status amr_compute_dt(amr_hierarchy* h, int buf, double* dt_dev);
 
-/* One SSP-RK3 stage (1, 2 or 3; async): fill ghosts of the stage input,
- * fused RHS + stage combination on every leaf, coarse/fine flux correction,
- * restriction of every non-leaf patch.  dt is read from the device scalar. */
+/* One SSP-RK3 stage (1, 2 or 3; async): fill the ghosts of the stage input
+ * that the stencils read (as amr_rhs), fused RHS + stage combination on
+ * every leaf (tiles of the finest level also restrict themselves into their
+ * parents), coarse/fine flux correction, restriction of every other
+ * non-leaf patch.  dt is read from the device scalar. */
 amr_status amr_rk_stage(amr_hierarchy* h, int stage, const double* dt_dev);
 
 /* dt (into *dt_dev) followed by the three stages (async).  In batched mode
