@@ -561,17 +561,21 @@ def main() -> int:
     log(f"[bench] warmup done ({args.warmup} steps)")
     use_graph = args.step_graph == "on"
     if mode == amr.EXEC_BATCHED and args.step_graph == "auto":
-        per = {}
+        # throughput (leaf cell-updates per second) rather than time per step:
+        # the mesh, and with it the work per step, changes between the windows
+        per, rate = {}, {}
         for g in (False, True):
             h.set_graph(g)
             advance(2, False)  # records the two step graphs (one per rate slot)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            advance(16, False)
+            c = advance(16, True)
             torch.cuda.synchronize()
             per[g] = (time.perf_counter() - t0) / 16
-        use_graph = per[True] < per[False]
-        log(f"[bench] step graph {per[True] * 1e6:.0f} us, eager {per[False] * 1e6:.0f} us: "
+            rate[g] = c / (16 * per[g])
+        use_graph = rate[True] > rate[False]
+        log(f"[bench] step graph {per[True] * 1e6:.0f} us ({rate[True] / 1e9:.3f} G cell-updates/s), "
+            f"eager {per[False] * 1e6:.0f} us ({rate[False] / 1e9:.3f} G): "
             f"{'graph' if use_graph else 'eager'}")
     h.set_graph(use_graph and mode == amr.EXEC_BATCHED)
     # pass 1: whole-job throughput (step graphs replayed, no instrumentation)

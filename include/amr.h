@@ -341,14 +341,14 @@ amr_status amr_cnn_mfma_selftest(amr_hierarchy* h, const uint16_t* a_dev, const 
  * one step are captured once (two graphs, one per CFL-rate slot) and
  * replayed; the graph holds kernel nodes only.  Batched launches of the
  * step's kernels read their work lists and live counts from a device list
- * directory that regrids rewrite, and a recorded launch holds a quarter
- * plus 256 more blocks than its list had (blocks past the live count exit),
- * so a regrid does not invalidate the graphs unless a list outgrows its
- * recorded grid; then the next step records them again (with the fused
- * halo off, the explicit ghost fill is sized by the leaf count and every
- * mesh change re-records them).  A change of tile variant, execution mode,
- * halo mode or dt pointer re-records them.  Enabling an enabled graph mode
- * keeps the recorded graphs.  Results are identical to eager launches. */
+ * directory that regrids rewrite, and after a regrid that changes the mesh
+ * the next replay first sets the grid of each list launch in the
+ * instantiated graph to the list's new length, so regrids never record the
+ * graphs again (with the fused halo off, the explicit ghost fill is sized by
+ * the leaf count and every mesh change re-records them).  A change of tile
+ * variant, execution mode, halo mode, tag dilation or dt pointer re-records
+ * them.  Enabling an enabled graph mode keeps the recorded graphs.  Results
+ * are identical to eager launches. */
 amr_status amr_set_graph(amr_hierarchy* h, int enable);
 /* Number of step graphs recorded since creation (test and profiling hook). */
 amr_status amr_graph_records(const amr_hierarchy* h, int* recorded);

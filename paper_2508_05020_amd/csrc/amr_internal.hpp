@@ -74,6 +74,10 @@ struct Kernels {
   // dir (nullable): list directory entry; with it `list` is the list buffer
   // and the list and its live count are read at run time, and `count` only
   // sizes the grid (at least the live count: one block per item)
+  // Grids (blocks) of the batched launches for a list of `count` items, for
+  // updating the launches of a recorded step graph after a regrid.
+  static int fill_cf_grid(const DevMesh& m, int count);
+  static int stage_grid(int count) { return ((count + kXcds - 1) / kXcds) * kXcds; }
   static void fill_cf(const DevMesh& m, double* U, const int* list, int count, const int* dir,
                       int* err, hipStream_t s);
   // fuse = halo nodes outside the patch with a same-level source are read

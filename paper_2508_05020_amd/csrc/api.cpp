@@ -60,18 +60,30 @@ struct amr_hierarchy {
   int exec_mode = AMR_EXEC_BATCHED;
   bool fuse_halo = true;  // stage kernel gathers halos itself (no fill pass)
   // hipGraphs of one batched step (dt + 3 stages), one per parity of the CFL
-  // rate double buffer.  Their launches read the work lists and counts from
-  // the list directory, so a regrid leaves them valid while every list fits
-  // the grid it was recorded with (rec_count: the counts at recording, see
-  // grid_count); a tile, mode or configuration change invalidates them.
+  // rate double buffer.  Their launches read the work lists and live counts
+  // from the list directory; after a regrid that changes the mesh the grid
+  // of each list launch is set to its new list length in the instantiated
+  // graph (gnodes: the launch nodes and the lists that size them, noted
+  // while recording), so a regrid never records them again.  A tile, mode
+  // or configuration change does.
+  struct GridNode {
+    hipGraphNode_t node;
+    int kind;        // kGn* below
+    int e[3], ne;    // directory entries whose counts add up to the items
+    int grid;        // blocks in the instantiated graph
+  };
   bool use_graph = false;
   bool capturing = false;
+  int cap_slot = 0;
   hipStream_t cap_stream = nullptr;
+  hipGraph_t step_graph[2] = {nullptr, nullptr};
   hipGraphExec_t step_exec[2] = {nullptr, nullptr};
   const double* step_exec_dt[2] = {nullptr, nullptr};
   bool step_exec_valid = false;
   bool step_exec_ok[2] = {false, false};
-  int rec_count[2][kDirEntries] = {};
+  std::vector<GridNode> gnodes[2];
+  long long mesh_version = 0;          // sync_tables calls so far
+  long long rec_version[2] = {-1, -1};  // mesh_version the graphs' grids match
   int step_records = 0;  // step graphs recorded so far
   // CFL rate of U^n: slot lam_cur holds it when lam_valid; the step being
   // run accumulates the next one into the other slot (slot 2: amr_compute_dt)
@@ -179,6 +191,8 @@ struct amr_hierarchy {
     for (int k = 0; k < 2; ++k) {
       if (step_exec[k]) (void)hipGraphExecDestroy(step_exec[k]);
       step_exec[k] = nullptr;
+      if (step_graph[k]) (void)hipGraphDestroy(step_graph[k]);
+      step_graph[k] = nullptr;
     }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     cap_stream = nullptr;
@@ -324,6 +338,7 @@ void build_devmesh(amr_hierarchy* h) {
 size_t req_flag_offset(int mp) { return ((2 * (size_t)mp + 63) / 64) * 64; }
 
 void sync_tables(amr_hierarchy* h, bool full) {
+  ++h->mesh_version;  // recorded step graphs resize their launches before the next replay
   amr::Forest& f = h->forest;
   const int mp = f.max_patches;
   // table deltas
@@ -643,23 +658,62 @@ void over_list(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F lau
 }
 
 // Grid size (in work items) of a batched launch over a directory list: the
-// live count, or while a step graph is recorded the count with headroom, so
-// that the recorded launch still covers the list after regrids that grow it
-// by up to a quarter plus 256 items (amr_step records the graph again when a
-// list outgrows it).  The blocks past the live count exit at once.
-int headroom(int count) { return count + count / 4 + 256; }
-
+// live count, or while a step graph is recorded at least 1, so that the
+// launch node exists and a later regrid can size it (blocks past the live
+// count exit at once).
 int grid_count(const amr_hierarchy* h, const amr::ListView& lv) {
-  return h->capturing ? headroom(lv.count) : lv.count;
+  return h->capturing ? std::max(lv.count, 1) : lv.count;
+}
+
+enum { kGnFill = 0, kGnStage = 1, kGnPost = 2, kGnRestrict = 3 };
+
+int dir_entry(const amr_hierarchy* h, const int* dir) { return (int)(dir - h->d_dir) / 2; }
+
+// Blocks of a launch of this kind over `items` work items (the launchers'
+// own grids; at least one block).
+int node_grid(const amr_hierarchy* h, int kind, int items) {
+  items = std::max(items, 1);
+  switch (kind) {
+    case kGnFill: return Kernels::fill_cf_grid(h->dm, items);
+    case kGnStage: return Kernels::stage_grid(items);
+    default: return items;
+  }
+}
+
+// While a step graph is recorded: the kernel node the last launch added, and
+// the directory entries whose live counts size it.
+void note_node(amr_hierarchy* h, int kind, int e0, int e1 = -1, int e2 = -1) {
+  if (!h->capturing) return;
+  hipStreamCaptureStatus st;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  HIP_OK(hipStreamGetCaptureInfo_v2(h->stream, &st, nullptr, nullptr, &deps, &nd));
+  if (st != hipStreamCaptureStatusActive || nd != 1)
+    throw HipError("step capture: expected one open node after a launch");
+  amr_hierarchy::GridNode g{};
+  g.node = deps[0];
+  g.kind = kind;
+  g.e[0] = e0;
+  g.e[1] = e1;
+  g.e[2] = e2;
+  g.ne = e2 >= 0 ? 3 : (e1 >= 0 ? 2 : 1);
+  int items = 0;
+  for (int k = 0; k < g.ne; ++k) items += h->h_dir[2 * g.e[k] + 1];
+  g.grid = node_grid(h, kind, items);
+  h->gnodes[h->cap_slot].push_back(g);
 }
 
 // The step's kernels: in batched mode one launch that reads the list and its
 // live count from the list directory (launch(list buffer, grid count,
 // directory entry)); per-patch mode as over_list.
 template <typename F>
-void over_list_dir(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, F launch) {
+void over_list_dir(amr_hierarchy* h, const amr::ListView& lv, int stride_ints, int kind,
+                   F launch) {
   if (h->exec_mode == AMR_EXEC_BATCHED) {
     launch(h->d_lists, grid_count(h, lv), lv.dir);
+    h->check_launch();
+    note_node(h, kind, dir_entry(h, lv.dir));
+    return;
   } else {
     for (int i = 0; i < lv.count; ++i)
       launch(lv.ptr + (long long)i * stride_ints, 1, (const int*)nullptr);
@@ -678,7 +732,7 @@ void do_fill(amr_hierarchy* h, int buf, const amr::ListView& lv, bool coarse_onl
 // one-directional; edge and corner regions are read by no stencil)
 void stage_fill(amr_hierarchy* h, int buf) {
   if (h->fuse_halo) {
-    over_list_dir(h, h->cffaces, 2, [&](const int* p, int c, const int* dir) {
+    over_list_dir(h, h->cffaces, 2, kGnFill, [&](const int* p, int c, const int* dir) {
       Kernels::fill_cf(h->dm, h->U[buf], p, c, dir, h->d_flags, h->stream);
     });
   } else {
@@ -688,7 +742,7 @@ void stage_fill(amr_hierarchy* h, int buf) {
 
 void do_restrict(amr_hierarchy* h, int buf) {
   for (int l = h->forest.nlev - 1; l >= 1; --l)
-    over_list_dir(h, h->restr[l], 1, [&](const int* p, int c, const int* dir) {
+    over_list_dir(h, h->restr[l], 1, kGnRestrict, [&](const int* p, int c, const int* dir) {
       Kernels::restrict_level(h->dm, h->U[buf], p, c, dir, h->stream);
     });
 }
@@ -705,7 +759,7 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
   stage_fill(h, s);
   const Kernels::TileVariant tv = Kernels::variant(h->dm.tile);
   const int tcells = tv.tx * tv.ty * tv.tz;
-  over_list_dir(h, h->tiles, 2, [&](const int* p, int c, const int* dir) {
+  over_list_dir(h, h->tiles, 2, kGnStage, [&](const int* p, int c, const int* dir) {
     hipEvent_t a = nullptr, b = nullptr;
     if (h->profiling) h->prof_pair(&a, &b, (long long)c * tcells);
     Kernels::stage(h->dm, stage, h->U[s], h->U[0], h->U[d], h->fr, p, c, dir, dt, h->fuse_halo,
@@ -722,8 +776,9 @@ void do_stage(amr_hierarchy* h, int stage, const double* dt,
                   h->reflux.dir, lup, true, dt, w[stage], stage == 3 ? lam_next : nullptr,
                   h->stream);
     h->check_launch();
+    note_node(h, kGnPost, kDirReflux, kDirPairs, kDirSingles);
     for (int l = lup - 1; l >= 1; --l)
-      over_list_dir(h, h->restr[l], 1, [&](const int* p, int c, const int* dir) {
+      over_list_dir(h, h->restr[l], 1, kGnRestrict, [&](const int* p, int c, const int* dir) {
         Kernels::restrict_level(h->dm, h->U[d], p, c, dir, h->stream);
       });
   } else {
@@ -773,7 +828,7 @@ void do_tag(amr_hierarchy* h, int buf, uint8_t* refine, uint8_t* coarsen, uint8_
   // none); else full fills
   const bool fuse = h->fuse_halo;
   if (fuse) {
-    over_list_dir(h, h->cfregions, 2, [&](const int* p, int c, const int* dir) {
+    over_list_dir(h, h->cfregions, 2, kGnFill, [&](const int* p, int c, const int* dir) {
       Kernels::fill_cf(h->dm, h->U[buf], p, c, dir, h->d_flags, h->stream);
     });
   } else {
@@ -1186,7 +1241,7 @@ amr_status amr_rhs(amr_hierarchy* h, int buf, double* rhs_dev) {
   if (!h || !buf_ok(buf) || !rhs_dev) return AMR_E_ARG;
   return guarded(h, [&]() -> amr_status {
     stage_fill(h, buf);
-    over_list_dir(h, h->tiles, 2, [&](const int* p, int c, const int* dir) {
+    over_list_dir(h, h->tiles, 2, kGnStage, [&](const int* p, int c, const int* dir) {
       Kernels::stage(h->dm, amr::kModeRHS, h->U[buf], h->U[0], rhs_dev, h->fr, p, c, dir, h->d_dt,
                      h->fuse_halo, nullptr, h->d_cfmask, h->stream);
     });
@@ -1228,17 +1283,15 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
         h->step_exec_ok[0] = h->step_exec_ok[1] = false;
         h->step_exec_valid = true;
       }
-      // a list that outgrew the grid its launch was recorded with
-      bool fits = true;
-      for (int e = 0; e < kDirEntries; ++e)
-        fits = fits && h->h_dir[2 * e + 1] <= headroom(h->rec_count[cur][e]);
-      if (!h->step_exec_ok[cur] || h->step_exec_dt[cur] != dt || !fits) {
+      if (!h->step_exec_ok[cur] || h->step_exec_dt[cur] != dt) {
         if (!h->cap_stream) HIP_OK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipStream_t user = h->stream;
         h->stream = h->cap_stream;
         hipGraph_t g = nullptr;
+        h->gnodes[cur].clear();
         HIP_OK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
         h->capturing = true;
+        h->cap_slot = cur;
         try {
           do_step(h, dt, cur);
         } catch (...) {
@@ -1246,20 +1299,38 @@ amr_status amr_step(amr_hierarchy* h, double* dt_dev) {
           (void)hipStreamEndCapture(h->stream, &g);
           if (g) (void)hipGraphDestroy(g);
           h->stream = user;
+          h->gnodes[cur].clear();
           throw;
         }
         h->capturing = false;
         HIP_OK(hipStreamEndCapture(h->stream, &g));
         h->stream = user;
-        for (int e = 0; e < kDirEntries; ++e) h->rec_count[cur][e] = h->h_dir[2 * e + 1];
         if (h->step_exec[cur]) HIP_OK(hipGraphExecDestroy(h->step_exec[cur]));
         h->step_exec[cur] = nullptr;
-        const hipError_t e = hipGraphInstantiate(&h->step_exec[cur], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        HIP_OK(e);
+        if (h->step_graph[cur]) HIP_OK(hipGraphDestroy(h->step_graph[cur]));
+        // the recorded graph stays alive: its kernel nodes are the handles
+        // through which a regrid resizes the instantiated launches
+        h->step_graph[cur] = g;
+        HIP_OK(hipGraphInstantiate(&h->step_exec[cur], g, nullptr, nullptr, 0));
         h->step_exec_ok[cur] = true;
         h->step_exec_dt[cur] = dt;
+        h->rec_version[cur] = h->mesh_version;
         ++h->step_records;
+      } else if (h->rec_version[cur] != h->mesh_version) {
+        // the lists changed: each list launch gets the grid of its new length
+        for (auto& gn : h->gnodes[cur]) {
+          int items = 0;
+          for (int k = 0; k < gn.ne; ++k) items += h->h_dir[2 * gn.e[k] + 1];
+          const int grid = node_grid(h, gn.kind, items);
+          if (grid == gn.grid) continue;
+          hipKernelNodeParams p{};
+          HIP_OK(hipGraphKernelNodeGetParams(gn.node, &p));
+          p.gridDim = dim3(grid);
+          HIP_OK(hipGraphExecKernelNodeSetParams(h->step_exec[cur], gn.node, &p));
+          HIP_OK(hipGraphKernelNodeSetParams(gn.node, &p));
+          gn.grid = grid;
+        }
+        h->rec_version[cur] = h->mesh_version;
       }
       HIP_OK(hipGraphLaunch(h->step_exec[cur], h->stream));
     }

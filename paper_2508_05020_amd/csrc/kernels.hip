@@ -954,6 +954,23 @@ __global__ __launch_bounds__(256) void k_check(DevMesh m, const double* __restri
     else hipLaunchKernelGGL(KERNEL<3>, GRID, BLOCK, 0, STREAM, __VA_ARGS__);             \
   } while (0)
 
+// Regions per block of the coarse/fine fill launch for this mesh (the
+// kernel choice of fill_cf below).
+static int fill_cf_per_block(const DevMesh& m) {
+  if (m.dim == 1) return 1;
+  if (m.dim == 2) {
+    int nmax = 0;
+    for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
+    return nmax <= 16 ? 1 : 2;
+  }
+  return 4;
+}
+
+int Kernels::fill_cf_grid(const DevMesh& m, int count) {
+  const int g = fill_cf_per_block(m);
+  return (count + g - 1) / g;
+}
+
 void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, const int* dir,
                       int* err, hipStream_t s) {
   if (count <= 0) return;

@@ -1045,7 +1045,7 @@ void Kernels::stage(const DevMesh& m, int mode, const double* Uin, const double*
   if (count <= 0) return;
   // one block per work item (`count` may exceed the live count read from the
   // directory), in whole groups of kXcds blocks (see xcd_item)
-  const int nb = ((count + kXcds - 1) / kXcds) * kXcds;
+  const int nb = stage_grid(count);
   const bool chr = m.scheme == AMR_SCHEME_CHAR;
 #define AMR_STAGE_K(D, TX, TY, TZ, NT, F, B, C)                                                \
   do {                                                                                          \

@@ -390,10 +390,10 @@ def _coarsenable(o, table):
 def test_graph_replays_equal_eager_bitwise(name, amr):
     """Step graphs (captured once, replayed across regrids) against eager
     launches: every replay, with eager work (tagging, regrids, host syncs) in
-    between, gives the eager result bit for bit.  A regrid that coarsens one
-    patch and a later one that refines it again change the mesh within the
-    recorded grids and record no new graph; plain regrids after them may grow
-    a list past its recorded grid (then the graphs are recorded again)."""
+    between, gives the eager result bit for bit, and no regrid records a new
+    graph: a regrid that coarsens one patch, a later one that refines it
+    again, and plain regrids after them (which may grow any list) only
+    resize the recorded launches."""
     o, hg, pg, _ = _pair(name, amr)
     _, he, pe, _ = _pair(name, amr)
     hg.set_graph(True)
@@ -430,6 +430,7 @@ def test_graph_replays_equal_eager_bitwise(name, amr):
             assert set(pg) < mesh0                      # the children removed
         if s == 4:
             assert set(pg) == mesh0                     # and made again
+    assert hg.graph_records() == 2
 
 
 @pytest.mark.parametrize("name,scheme", [("2d", "weno"), ("3d", "weno"), ("3d-uneven", "weno"),
