@@ -624,18 +624,15 @@ void sync_tables(amr_hierarchy* h, bool full) {
   std::fill(sm, sm + 2 * mp, (uint8_t)0);
   for (int i = 0; i < nref; ++i) sm[L[r0 + 2 * i]] = (uint8_t)L[r0 + 2 * i + 1];
   uint8_t* sw = sm + mp;
-  for (int pid : order) {
-    if (!f.is_leaf(pid)) continue;
-    const int l = f.level[pid];
-    const int c[3] = {f.coord[3 * pid], f.coord[3 * pid + 1], f.coord[3 * pid + 2]};
-    int w = sm[pid];
+  for (int pid : order)
+    if (f.is_leaf(pid)) sw[pid] = sm[pid];
+  // a face of a leaf across which no same-level patch lies inside the domain
+  // is exactly a face region of the prolonged-ghost list
+  for (int i = cf1; i < k0; i += 2) {
+    const int code = L[i + 1];
+    const int o[3] = {code % 3 - 1, (code / 3) % 3 - 1, (code / 9) % 3 - 1};
     for (int j = 0; j < f.dim; ++j)
-      for (int side = 0; side < 2; ++side) {
-        const int o = side ? 1 : -1;
-        if (f.neighbour(l, c, j == 0 ? o : 0, j == 1 ? o : 0, j == 2 ? o : 0) == -1)
-          w |= 1 << (2 * j + side);
-      }
-    sw[pid] = (uint8_t)w;
+      if (o[j] != 0) sw[L[i]] |= (uint8_t)(1 << (2 * j + (o[j] > 0 ? 1 : 0)));
   }
   HIP_OK(hipMemcpyAsync(h->d_cfmask, sm, 2 * mp, hipMemcpyHostToDevice, h->stream));
   if (np > 0) {
@@ -886,8 +883,9 @@ amr_status regrid_impl(amr_hierarchy* h, const uint8_t* refine, const uint8_t* c
   }
   h->last_created = created;
   // the recorded step graphs stay valid: their launches read the lists and
-  // counts from the list directory that sync_tables rewrites (the explicit
-  // ghost fill of the unfused path is sized by the leaf count)
+  // counts from the list directory that sync_tables rewrites, and the next
+  // replay resizes them (the explicit ghost fill of the unfused path is
+  // sized by the leaf count)
   if (!h->fuse_halo) h->step_exec_valid = false;
   h->lam_valid = false;
   sync_tables(h, false);

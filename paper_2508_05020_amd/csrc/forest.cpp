@@ -399,27 +399,33 @@ std::vector<int> Forest::sorted_active() const {
     }
     return out;
   }
-  // (level, z, y, x, pid) packed into one 64-bit key when the fields fit
-  // (level < 16, coordinates < 2^14, pid < 2^17), else the comparator
-  bool packed = max_patches <= (1 << 17);
-  for (int l = 0; l < nlev; ++l) packed &= np[l] <= (1 << 14);
-  if (packed) {
+  // (level, z, y, x, pid) packed into one 64-bit key when the fields fit,
+  // each field as wide as this forest needs, else the comparator
+  auto width = [](long long v) {  // bits for the values 0 .. v - 1
+    int b = 0;
+    while (b < 62 && (1LL << b) < v) ++b;
+    return b;
+  };
+  int npmax = 1;
+  for (int l = 0; l < nlev; ++l) npmax = std::max(npmax, np[l]);
+  const int bp = width(max_patches), bc = width(npmax), bl = width(nlev);
+  const int ob = bl + dim * bc;  // ordering bits above the pid field
+  if (bp + ob <= 64) {
     std::vector<uint64_t> keys;
     for (int pid = 0; pid < max_patches; ++pid) {
       if (!active[pid]) continue;
-      keys.push_back(((uint64_t)level[pid] << 59) | ((uint64_t)coord[3 * pid + 2] << 45) |
-                     ((uint64_t)coord[3 * pid + 1] << 31) | ((uint64_t)coord[3 * pid] << 17) |
-                     (uint64_t)pid);
+      uint64_t k = (uint64_t)level[pid];
+      for (int j = dim - 1; j >= 0; --j) k = (k << bc) | (uint64_t)coord[3 * pid + j];
+      keys.push_back((k << bp) | (uint64_t)pid);
     }
     if (keys.size() < 4096) {
       std::sort(keys.begin(), keys.end());
     } else {
-      // LSD radix sort on the 46 ordering bits above the pid field (17..62),
-      // three 16-bit digits; the keys are distinct, so the order is the
-      // comparison sort's
+      // LSD radix sort on the ordering bits, 16-bit digits; the keys are
+      // distinct, so the order is the comparison sort's
       std::vector<uint64_t> tmp(keys.size());
       std::vector<uint32_t> cnt(65537);
-      for (const int sh : {17, 33, 49}) {
+      for (int sh = bp; sh < bp + ob; sh += 16) {
         std::fill(cnt.begin(), cnt.end(), 0u);
         for (const uint64_t k : keys) ++cnt[((k >> sh) & 0xffffu) + 1];
         for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
@@ -428,7 +434,8 @@ std::vector<int> Forest::sorted_active() const {
       }
     }
     out.reserve(keys.size());
-    for (uint64_t k : keys) out.push_back((int)(k & ((1u << 17) - 1)));
+    const uint64_t pm = (bp >= 64) ? ~0ull : ((1ull << bp) - 1);
+    for (uint64_t k : keys) out.push_back((int)(k & pm));
     return out;
   }
   for (int pid = 0; pid < max_patches; ++pid)
@@ -439,13 +446,30 @@ std::vector<int> Forest::sorted_active() const {
 
 
 namespace {
-// Morton code of a patch position: the bits of x, y, z interleaved, x
-// lowest (13 bits per coordinate).
+// The low bits of v spread to every second (third) bit position.
+uint64_t spread2(uint64_t v) {
+  v &= 0xffffffffull;
+  v = (v | (v << 16)) & 0x0000ffff0000ffffull;
+  v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
+  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
+  v = (v | (v << 2)) & 0x3333333333333333ull;
+  return (v | (v << 1)) & 0x5555555555555555ull;
+}
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x001f00000000ffffull;
+  v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  return (v | (v << 2)) & 0x1249249249249249ull;
+}
+// Morton code of a patch position: bit b of coordinate j at bit b dim + j
+// (x lowest; 13 bits per coordinate).
 uint64_t morton(const int* c, int dim) {
-  uint64_t m = 0;
-  for (int b = 0; b < 13; ++b)
-    for (int j = 0; j < dim; ++j) m |= (uint64_t)((c[j] >> b) & 1) << (b * dim + j);
-  return m;
+  const uint64_t m13 = (1u << 13) - 1;
+  if (dim == 1) return (uint64_t)c[0] & m13;
+  if (dim == 2) return spread2(c[0] & m13) | (spread2(c[1] & m13) << 1);
+  return spread3(c[0] & m13) | (spread3(c[1] & m13) << 1) | (spread3(c[2] & m13) << 2);
 }
 }  // namespace
 
