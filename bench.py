@@ -328,19 +328,21 @@ def learned_gain(args) -> int:
         eseed = workloads.seed_for(int(num), 1)
     else:
         n = trained["n"]
+        base = args.learned_base or (64 if dim == 2 else 16)
         ecfg = workloads.AMRConfig(
             name=f"{'quadrants-blobs' if dim == 2 else 'blasts-perturbed'}-4lev", dim=dim,
-            base_cells=64 if dim == 2 else 16, patch_cells=[n] * 4, periodic=[True] * dim,
+            base_cells=base, patch_cells=[n] * 4, periodic=[True] * dim,
             ic="quadrants_blobs" if dim == 2 else "blasts_perturbed", tag_buffer=b,
-            max_patches=16384 if dim == 2 else 32768)
+            max_patches=(16384 * max(1, (base // 64) ** 2) if dim == 2
+                         else 32768 * max(1, (base // 16) ** 3 // 2)))
         eseed = seed_eval
     wide = min(3, math.ceil(H * ecfg.cfl))
     policies = [("P_plain2_per_patch", 2, "plain", amr.EXEC_PER_PATCH, None),
                 ("B_plain2", 2, "plain", amr.EXEC_BATCHED, None),
                 (f"B{H}_plain{H}_dilation{wide}", H, "plain", amr.EXEC_BATCHED, wide),
                 (f"BL_learned{H}", H, "learned", amr.EXEC_BATCHED, None)]
-    if args.learned_eval and dim == 3:
-        policies = policies[1:]  # one launch per patch and phase: hours on a 3D workload
+    if (args.learned_eval and dim == 3) or args.learned_base:
+        policies = policies[1:]  # one launch per patch and phase: hours on a large workload
     results = compare_policies(ecfg, eseed, args.steps, policies, trained, rounds)
     L = results[f"BL_learned{H}"]["wall_per_tsim"]
     out = {"metric": "wall-clock per unit simulated time, plain vs learned regridding",
@@ -468,6 +470,9 @@ def main() -> int:
     ap.add_argument("--learned-eval", default=None,
                     help="evaluate the policies on this workload (e.g. c5) instead of the "
                          "training configuration; per-patch launches are skipped there")
+    ap.add_argument("--learned-base", type=int, default=None,
+                    help="level-0 cells per dimension of the evaluation hierarchy of --learned "
+                         "(default 64 in 2D, 16 in 3D)")
     ap.add_argument("--learned-dim", type=int, default=2, choices=[2, 3],
                     help="2D quadrants + blobs or 3D blast waves + perturbations")
     ap.add_argument("--seed-eval", type=int, default=None,
