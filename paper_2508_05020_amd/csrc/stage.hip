@@ -235,19 +235,6 @@ __device__ __forceinline__ void node_store(const DevMesh& m, const double* u, do
   }
 }
 
-// The same, keeping what was stored in `keep` as well.
-template <int D, bool CHAR>
-__device__ __forceinline__ void node_store_keep(const DevMesh& m, const double* u, double* sP,
-                                                int next, int idx, double* keep) {
-  if constexpr (CHAR) {
-#pragma unroll
-    for (int v = 0; v < D + 2; ++v) keep[v] = u[v];
-  } else {
-    node_primitives<D>(m, u, keep);
-  }
-#pragma unroll
-  for (int k = 0; k < D + 2; ++k) sP[k * next + idx] = keep[k];
-}
 
 // Same-level patches around the tile's patch, by offset code
 // (o0+1) + 3 (o1+1) + 9 (o2+1), o in {-1,0,1}^D (periodic wrap), as the
@@ -596,7 +583,10 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
       else if constexpr (J == 1) tang = (o[0] + t0) + __mul24(n, o[2] + t2);
       else tang = (o[0] + t0) + __mul24(n, o[1] + t1);
     }
-    double Gps[NV], Gms[NV];
+    // the flux registers of this face (variable v at v nface + tang of the
+    // face's block; 32-bit offsets, 24-bit products), written per variable
+    const bool lo = i == 0 && lo_reg, hi = i == n - 1 && hi_reg;
+    double* fb = frp + __mul24((J * 2 + (hi ? 1 : 0)) * NV, nface) + tang;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       // edge fluxes are stored doubled (the Rusanov 1/2 is applied here, as
@@ -606,20 +596,7 @@ __device__ __forceinline__ void cells_at(const double* sF, double* __restrict__ 
       const double Gp = fma(-c24, fma(-2.0, F0, Fm1) + Fp1, F0);
       const double Gm = fma(-c24, fma(-2.0, Fm1, Fm2) + F0, Fm1);
       acc[cc][v] = fma(-(Gp - Gm), half_inv_h, acc[cc][v]);
-      Gps[v] = Gp;
-      Gms[v] = Gm;
-    }
-    // the flux registers of this face (variable v at v nface + tang of the
-    // face's block; 32-bit offsets, 24-bit products)
-    if (i == 0 && lo_reg) {
-      double* fb = frp + __mul24((J * 2 + 0) * NV, nface) + tang;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fb[__mul24(v, nface)] = 0.5 * Gms[v];
-    }
-    if (i == n - 1 && hi_reg) {
-      double* fb = frp + __mul24((J * 2 + 1) * NV, nface) + tang;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) fb[__mul24(v, nface)] = 0.5 * Gps[v];
+      if (lo || hi) fb[__mul24(v, nface)] = 0.5 * (hi ? Gp : Gm);
     }
   }
 }
@@ -664,10 +641,11 @@ __device__ __forceinline__ void edges_dir(const DevMesh& m, const double* sP, do
 // extended-box layout.  The tile's own nodes come first in the thread order
 // and the 8 halo layers after them, so that a wave holds nodes of one kind
 // (the tile's own nodes are read straight from the patch); every thread
-// issues the loads of all its nodes before converting any.  Thread t < NCELL
-// holds tile node t in every direction: it converts it once (J = 0), keeps
-// the values in `keep` and stores them again for J = 1, 2 (primitive
-// schemes).
+// issues the loads of all its nodes before converting any.  For the
+// primitive schemes thread t < NCELL keeps the conserved values of tile
+// node t from direction x in `keep` (they are also the stage input of cell
+// t for the epilogue); their y and z boxes load only the halo layers
+// (halo_issue, halo_store).
 template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool CHAR>
 __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restrict__ Uin,
                                          const double* __restrict__ Pin, int n, int full,
@@ -686,6 +664,7 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
   constexpr int NNODE = NC + 8 * HL;           // nodes of the extended box
   // the characteristic scheme's kernel has no registers to spare for it
   constexpr bool KEEP = !CHAR;
+  static_assert(J == 0 || !KEEP, "y and z boxes of the primitive schemes load their halo only");
   constexpr int ITER = (NNODE + NT - 1) / NT;
   double u[ITER][NV];
   int lidx[ITER];
@@ -711,7 +690,6 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
     const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
     lidx[k] = (t[0] + (J == 0 ? 4 : 0)) + E0 * ((t[1] + (J == 1 ? 4 : 0)) +
                                                 E1 * (t[2] + (J == 2 ? 4 : 0)));
-    if (KEEP && J > 0 && idx < NC) continue;  // kept since direction x
     node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
   }
   static_assert(NT >= NC, "the tile's own nodes are the first item of each thread");
@@ -719,16 +697,79 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
   for (int k = 0; k < ITER; ++k) {
     if (lidx[k] < 0) continue;
     if (KEEP && k == 0 && (int)threadIdx.x < NC) {
-      if constexpr (J == 0) {
-        node_store_keep<D, CHAR>(m, u[0], sP, NEXT, lidx[0], keep);
-      } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sP[v * NEXT + lidx[0]] = keep[v];
-      }
-    } else {
-      node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
+      for (int v = 0; v < NV; ++v) keep[v] = u[0][v];
     }
+    node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
   }
+}
+
+// 3D primitive schemes, directions y and z: the 8 halo layers of the tile
+// extended along J (its own nodes are kept since x).  Their loads are issued
+// (halo_issue) before the previous direction's divergence is formed and
+// converted and stored (halo_store) after it, so that they are in flight
+// meanwhile.  Halo node h (layers -4..-1, then T_J..T_J+3, the two other
+// directions lower first) is item h / NT of thread h mod NT.
+template <int D, int TX, int TY, int TZ, int NT, int J>
+struct DirHalo {
+  using S = TileShape<D, TX, TY, TZ>;
+  static constexpr int NV = D + 2;
+  static constexpr int TJ = J == 0 ? S::T0 : (J == 1 ? S::T1 : S::T2);
+  static constexpr int HL = S::NCELL / TJ;                  // nodes of one layer
+  static constexpr int NH = 8 * HL;
+  static constexpr int ITER = (NH + NT - 1) / NT;
+  double u[ITER][NV];
+  int lidx[ITER];
+};
+
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE>
+__device__ __forceinline__ void halo_issue(const DevMesh& m, const double* __restrict__ Uin,
+                                           const double* __restrict__ Pin, int n, int full,
+                                           const int o[3], const int pc[3], int l,
+                                           const long long* sN,
+                                           DirHalo<D, TX, TY, TZ, NT, J>& h) {
+  using S = TileShape<D, TX, TY, TZ>;
+  using H = DirHalo<D, TX, TY, TZ, NT, J>;
+  static_assert(J > 0, "direction x loads the whole extended box");
+  constexpr int E0 = S::xpitch(J);
+  constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
+  constexpr int CA = S::T0;                    // extent of the lower cross direction (x)
+#pragma unroll
+  for (int k = 0; k < H::ITER; ++k) {
+    // threads past the last halo node load node NH - 1 again (no branch
+    // around the loads) and store nothing
+    const int h0 = threadIdx.x + k * NT;
+    const int hh = h0 < H::NH ? h0 : H::NH - 1;
+    const int layer = hh / H::HL;
+    const int r = hh - layer * H::HL;
+    int t[3];
+    t[J] = layer < 4 ? layer - 4 : H::TJ + layer - 4;
+    t[0] = r % CA;
+    t[J == 2 ? 1 : 2] = r / CA;
+    const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
+    h.lidx[k] = h0 < H::NH ? t[0] + E0 * ((t[1] + (J == 1 ? 4 : 0)) + E1 * (t[2] + (J == 2 ? 4 : 0)))
+                           : -1;
+    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, h.u[k]);
+  }
+}
+
+template <int D, int TX, int TY, int TZ, int NT, int J>
+__device__ __forceinline__ void halo_store(const DevMesh& m, const DirHalo<D, TX, TY, TZ, NT, J>& h,
+                                           const double* keep, double* sP) {
+  using S = TileShape<D, TX, TY, TZ>;
+  using H = DirHalo<D, TX, TY, TZ, NT, J>;
+  constexpr int E0 = S::xpitch(J);
+  constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
+  constexpr int NEXT = S::ext(J);
+  const int tid = threadIdx.x;
+  if (tid < S::NCELL) {
+    const int t0 = tid % S::T0, t1 = (tid / S::T0) % S::T1, t2 = tid / (S::T0 * S::T1);
+    node_store<D, false>(m, keep, sP, NEXT,
+                         t0 + E0 * ((t1 + (J == 1 ? 4 : 0)) + E1 * (t2 + (J == 2 ? 4 : 0))));
+  }
+#pragma unroll
+  for (int k = 0; k < H::ITER; ++k)
+    if (h.lidx[k] >= 0) node_store<D, false>(m, h.u[k], sP, NEXT, h.lidx[k]);
 }
 
 // 1D/2D: edge fluxes and their divergence for direction J from the union
@@ -851,6 +892,10 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
+  // 3D primitive schemes: the stage input of this thread's own cell, kept
+  // from the first node load (see load_dir)
+  constexpr bool KEPT = !UNION && !CHAR;
+  double keep[NV];
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
@@ -870,21 +915,34 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     // 3D, direction by direction: the next direction's nodes are loaded in
     // the phase that forms the previous direction's divergence (sP is free
     // once the edges are done, sF is read), two block barriers per direction
-    double keep[NV];
     load_dir<D, TX, TY, TZ, NT, 0, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
                                                    keep);
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 0, false, CHAR>(m, sP, sF);
     __syncthreads();
-    load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
-                                                   keep);
-    cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
+    if constexpr (KEPT) {
+      DirHalo<D, TX, TY, TZ, NT, 1> h;
+      halo_issue<D, TX, TY, TZ, NT, 1, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, h);
+      cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
+      halo_store<D, TX, TY, TZ, NT, 1>(m, h, keep, sP);
+    } else {
+      load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
+                                                     keep);
+      cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
+    }
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 1, false, CHAR>(m, sP, sF);
     __syncthreads();
-    load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
-                                                   keep);
-    cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
+    if constexpr (KEPT) {
+      DirHalo<D, TX, TY, TZ, NT, 2> h;
+      halo_issue<D, TX, TY, TZ, NT, 2, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, h);
+      cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
+      halo_store<D, TX, TY, TZ, NT, 2>(m, h, keep, sP);
+    } else {
+      load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
+                                                     keep);
+      cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
+    }
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 2, false, CHAR>(m, sP, sF);
     __syncthreads();
@@ -935,10 +993,22 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
       if (mode == kModeRHS) {
         r[v] = Lv;
       } else if (mode == kModeStage1) {
-        r[v] = fma(dt, Lv, Un[a]);
+        // stage 1 combines with U^n, which is its input buffer within a step:
+        // then the kept stage input of the thread's own cell (cc = 0) serves
+        double un;
+        if constexpr (KEPT)
+          un = (cc == 0 && Un == Uin) ? keep[v] : Un[a];
+        else
+          un = Un[a];
+        r[v] = fma(dt, Lv, un);
       } else {
+        // the stage input of the cell: kept (cc = 0) or loaded
+        double ui;
+        if constexpr (KEPT)
+          ui = cc == 0 ? keep[v] : Uin[a];
+        else
+          ui = Uin[a];
         const double un = Un[a];
-        const double ui = Uin[a];
         r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
       out[a] = r[v];
