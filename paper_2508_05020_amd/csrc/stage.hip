@@ -72,14 +72,13 @@ __device__ __forceinline__ void sqrt_rsqrt_nr(double x, double& s, double& is) {
 }
 
 // Numerator and denominator of the nonlinear WENO5-JS combination of three
-// candidates q_k from their smoothness indicators b_k: the value is
-// sum(alpha_k q_k) / sum(alpha_k) with alpha_k = d_k / t_k, t_k = (eps +
-// b_k)^2 and d = (1, 10, 5)/16, evaluated as cross products (alpha_k times
+// candidates q_k from e_k = eps + b_k (b_k the smoothness indicators): the
+// value is sum(alpha_k q_k) / sum(alpha_k) with alpha_k = d_k / t_k, t_k =
+// e_k^2 and d = (1, 10, 5)/16, evaluated as cross products (alpha_k times
 // t0 t1 t2 / 16): num = t2 (t1 q0 + 10 t0 q1) + 5 t0 t1 q2, den = t2 (t1 +
 // 10 t0) + 5 t0 t1.
-__device__ __forceinline__ void weno_num_den(double b0, double b1, double b2, double q0, double q1,
-                                             double q2, double eps4, double& num, double& den) {
-  const double e0 = eps4 + b0, e1 = eps4 + b1, e2 = eps4 + b2;
+__device__ __forceinline__ void weno_num_den(double e0, double e1, double e2, double q0, double q1,
+                                             double q2, double& num, double& den) {
   const double t0 = e0 * e0, t1 = e1 * e1, t2 = e2 * e2;
   const double c0 = 10.0 * t0;
   const double p5 = 5.0 * (t0 * t1);
@@ -97,10 +96,12 @@ __device__ __forceinline__ void weno_num_den(double b0, double b1, double b2, do
 // a - c (centred), 3a - 4b + c (window right of it).  With the first
 // differences d_i = v_(i+1) - v_i, k_w = d_(w+1) - d_w and the three forms
 // are k + 2 d_(w+1), -(d_w + d_(w+1)) and k - 2 d_w, so the four windows
-// share their differences.  One reciprocal serves both sides: 1/(den_L
-// den_R) (the indicators are bounded below by eps, and eps is at least
-// 1e-20, so the product stays a normal number) times the other side's
-// denominator, and with it the final 1/8.  The scalings are powers of two.
+// share their differences.  The curvature term of a window (with eps) is
+// shared by the two sides where both use the window.  One reciprocal serves
+// both sides: 1/(den_L den_R) (the indicators are bounded below by eps, and
+// eps is at least 1e-20, so the product stays a normal number) times the
+// other side's denominator, and with it the final 1/8.  The scalings are
+// powers of two.
 __device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, double v3, double v4,
                                            double v5, double eps4, double& L, double& R) {
   const double qa = fma(15.0, v2, fma(-10.0, v1, 3.0 * v0));  // left, nodes v0..v2
@@ -110,22 +111,20 @@ __device__ __forceinline__ void weno5_pair(double v0, double v1, double v2, doub
   const double d0 = v1 - v0, d1 = v2 - v1, d2 = v3 - v2, d3 = v4 - v3, d4 = v5 - v4;
   const double k0 = d1 - d0, k1 = d2 - d1, k2 = d3 - d2, k3 = d4 - d3;
   constexpr double c4 = 4.0 * (13.0 / 12.0);
-  const double g0 = c4 * k0, g1 = c4 * k1, g2 = c4 * k2, g3 = c4 * k3;
+  // eps + curvature term of windows v0..v2, v1..v3, v2..v4, v3..v5
+  const double h0 = fma(c4 * k0, k0, eps4);
+  const double h1 = fma(c4 * k1, k1, eps4);
+  const double h2 = fma(c4 * k2, k2, eps4);
+  const double h3 = fma(c4 * k3, k3, eps4);
   const double sl0 = fma(2.0, d1, k0);   // window v0..v2, node v2
   const double sl1 = d1 + d2;            // window v1..v3, centred
   const double sl2 = fma(-2.0, d2, k2);  // window v2..v4, node v2
   const double sr0 = fma(-2.0, d3, k3);  // window v3..v5, node v3
   const double sr1 = d2 + d3;            // window v2..v4, centred
   const double sr2 = fma(2.0, d2, k1);   // window v1..v3, node v3
-  const double bl0 = fma(g0, k0, sl0 * sl0);
-  const double bl1 = fma(g1, k1, sl1 * sl1);
-  const double bl2 = fma(g2, k2, sl2 * sl2);
-  const double br0 = fma(g3, k3, sr0 * sr0);
-  const double br1 = fma(g2, k2, sr1 * sr1);
-  const double br2 = fma(g1, k1, sr2 * sr2);
   double nl, dl, nr, dr;
-  weno_num_den(bl0, bl1, bl2, qa, qb, qc, eps4, nl, dl);
-  weno_num_den(br0, br1, br2, qd, qc, qb, eps4, nr, dr);
+  weno_num_den(fma(sl0, sl0, h0), fma(sl1, sl1, h1), fma(sl2, sl2, h2), qa, qb, qc, nl, dl);
+  weno_num_den(fma(sr0, sr0, h3), fma(sr1, sr1, h2), fma(sr2, sr2, h1), qd, qc, qb, nr, dr);
   const double inv = rcp_nr(dl * dr) * 0.125;
   L = nl * (dr * inv);
   R = nr * (dl * inv);
@@ -895,7 +894,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
   // 3D primitive schemes: the stage input of this thread's own cell, kept
   // from the first node load (see load_dir)
   constexpr bool KEPT = !UNION && !CHAR;
-  double keep[NV];
+  double keep[NV], un0[NV];
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
@@ -946,6 +945,24 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 2, false, CHAR>(m, sP, sF);
     __syncthreads();
+    if constexpr (KEPT) {
+      // U^n of the thread's own cell for the combination, loaded while the
+      // last divergence is formed (the kept stage input when U^n is it)
+      const int tid = threadIdx.x;
+      if (mode != kModeRHS && tid < S::NCELL) {
+        if (Un == Uin) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) un0[v] = keep[v];
+        } else {
+          const int t0 = tid % S::T0, t1 = (tid / S::T0) % S::T1, t2 = tid / (S::T0 * S::T1);
+          const double* p = Un + base + box_off<D>(full, o[0] + t0 + NG, o[1] + t1 + NG,
+                                                   o[2] + t2 + NG);
+          const int vs = var_stride<D>(full);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) un0[v] = p[v * vs];
+        }
+      }
+    }
     cells_at<D, TX, TY, TZ, NT, 2>(sF, frp, n, o, acc, L.inv_h, wmask);
   }
 
@@ -993,22 +1010,13 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
       if (mode == kModeRHS) {
         r[v] = Lv;
       } else if (mode == kModeStage1) {
-        // stage 1 combines with U^n, which is its input buffer within a step:
-        // then the kept stage input of the thread's own cell (cc = 0) serves
-        double un;
-        if constexpr (KEPT)
-          un = (cc == 0 && Un == Uin) ? keep[v] : Un[a];
-        else
-          un = Un[a];
+        // U^n and the stage input of the cell: held for the thread's own
+        // cell (cc = 0) in 3D, else loaded
+        const double un = (KEPT && cc == 0) ? un0[v] : Un[a];
         r[v] = fma(dt, Lv, un);
       } else {
-        // the stage input of the cell: kept (cc = 0) or loaded
-        double ui;
-        if constexpr (KEPT)
-          ui = cc == 0 ? keep[v] : Uin[a];
-        else
-          ui = Uin[a];
-        const double un = Un[a];
+        const double un = (KEPT && cc == 0) ? un0[v] : Un[a];
+        const double ui = (KEPT && cc == 0) ? keep[v] : Uin[a];
         r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
       out[a] = r[v];
