@@ -355,7 +355,7 @@ amr_status amr_graph_records(const amr_hierarchy* h, int* recorded);
 
 /* Tile variants of the fused stage kernel (cells per tile and block size):
  * 0: 16 (1D, 64 threads), 1: 8 (1D), 2: 16x16 (2D, 320), 3: 16x8 (2D, 192),
- * 4: 8x8 (2D, 128), 5: 8x8x8 (3D, 704), 6: 8x8x4 (3D, 448), 7: 4x4x4 (3D, 128);
+ * 4: 8x8 (2D, 128), 5: 8x8x8 (3D, 768), 6: 8x8x4 (3D, 448), 7: 4x4x4 (3D, 128);
  * 8, 9, 10: 16x16, 16x8, 8x8 (2D) computing the x and y edge fluxes in one
  * sweep (more LDS, fewer block barriers).
  * A variant is admissible when its extents divide every level's patch edge.

@@ -985,10 +985,12 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, c
       // refined patches of edge 16 or less: one fine cell per thread (a side
       // region is 4 n = 64 cells); wider ones: by coarse cell, two regions
       // per wave (a side region of a 32^2 patch is 64 coarse cells).  Level 0
-      // has no prolonged ghosts.  Per launch: C2 (16^2) 7.2 us per fine
-      // cell, 10.1 / 8.5 / 11.1 us by coarse cell with 1 / 2 / 8 regions per
-      // block; C4 (32^2) 30.3 us per fine cell (128 threads), 34.1 / 25.4 us
-      // by coarse cell with 1 / 2 regions per block.
+      // has no prolonged ghosts.  Per launch on a 3-level 2D hierarchy of
+      // base 256^2 with 32/16/16 patches: 7.2 us per fine cell, 10.1 / 8.5 /
+      // 11.1 us by coarse cell with 1 / 2 / 8 regions per block; on a
+      // 5-level one of base 512^2 with 32^2 patches: 30.3 us per fine cell
+      // (128 threads), 34.1 / 25.4 us by coarse cell with 1 / 2 regions per
+      // block.
       int nmax = 0;
       for (int l = 1; l < m.nlev; ++l) nmax = std::max(nmax, m.lv[l].n);
       if (nmax <= 16)
@@ -1000,8 +1002,9 @@ void Kernels::fill_cf(const DevMesh& m, double* U, const int* list, int count, c
     default:
       // one thread per coarse cell, 4 regions per wave: a region of an 8^3
       // patch covers 8, 16 or 32 coarse cells and one of a 16^3 patch 8 to
-      // 128 (per launch on C5: 2.12 ms with 4 regions per block, 2.19 with
-      // 8, 2.27 with 16)
+      // 128 (per launch on a four-level 3D hierarchy of base 256^3 with
+      // 32/16/16/8 patches: 2.12 ms with 4 regions per block, 2.19 with 8,
+      // 2.27 with 16)
       launch(k_fill_cf_coarse<3, 64, 4>, 64, 4);
       break;
   }
@@ -1014,8 +1017,6 @@ void Kernels::fill(const DevMesh& m, double* U, const int* list, int count, int*
                    coarse_only ? 1 : 0);
 }
 
-// Stage-kernel tile variants: thread counts cover the edges of one
-// direction of the tile in one pass (multiples of 64).
 void Kernels::reflux(const DevMesh& m, int mode, double* out, const double* fr,
                      const int* list, int count, const double* dt, double w,
                      unsigned long long* lam_next, hipStream_t s) {
