@@ -29,6 +29,15 @@ namespace {
 // fused right-hand side + SSP-RK3 stage on (pid, tile) work items
 // ---------------------------------------------------------------------------
 
+// threadIdx.x hidden from the optimiser: the index arithmetic of a phase is
+// then formed in that phase instead of being shared with another direction's
+// phase and held in registers across the edge phases, where they run out
+__device__ __forceinline__ int phase_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // 1/x from the hardware reciprocal estimate refined by two Newton steps
 // (relative error near one ulp); used where correct rounding is not required.
 __device__ __forceinline__ double rcp_nr(double x) {
@@ -307,6 +316,42 @@ __device__ __forceinline__ void node_conserved(const DevMesh& m, const double* _
   const int off = box_off<D>(full, c[0] + NG, c[1] + NG, c[2] + NG);
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = Pin[v * vs + off];
+}
+
+// node_conserved for a node of a 3D tile's halo along J (or of the tile
+// itself): only its J component can lie outside the patch, so the neighbour
+// code and the wrap or clamp are formed for that component alone.
+template <int D, int J, bool FUSE>
+__device__ __forceinline__ void node_conserved_dir(const DevMesh& m,
+                                                   const double* __restrict__ Uin,
+                                                   const double* __restrict__ Pin, int n,
+                                                   int full, const int c[3], const int pc[3],
+                                                   int l, const long long* sNB, double* u) {
+  constexpr int NV = D + 2;
+  constexpr int CENTRE = D == 1 ? 1 : (D == 2 ? 4 : 13);
+  constexpr int MULJ = J == 0 ? 1 : (J == 1 ? 3 : 9);
+  const int vs = var_stride<D>(full);
+  const double* src = Pin;
+  int cj = c[J];
+  if (FUSE && (unsigned)cj >= (unsigned)n) {
+    int o = cj < 0 ? -1 : 1;
+    int lj = cj < 0 ? cj + n : cj - n;
+    if (!m.periodic[J] && (unsigned)(pc[J] + o) >= (unsigned)m.lv[l].np) {
+      o = 0;
+      lj = cj < 0 ? 0 : n - 1;
+    }
+    const long long sb = sNB[CENTRE + o * MULJ];
+    // no same-level source: the prolonged ghost value in the patch's own
+    // ghost layer (position unchanged)
+    if (sb >= 0) {
+      src = Uin + sb;
+      cj = lj;
+    }
+  }
+  const int off = box_off<D>(full, (J == 0 ? cj : c[0]) + NG, (J == 1 ? cj : c[1]) + NG,
+                             (J == 2 ? cj : c[2]) + NG);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u[v] = src[v * vs + off];
 }
 
 // 1D/2D: primitives of the tile plus 4-node halos in every direction
@@ -692,7 +737,7 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
     const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
     lidx[k] = (t[0] + (J == 0 ? 4 : 0)) + E0 * ((t[1] + (J == 1 ? 4 : 0)) +
                                                 E1 * (t[2] + (J == 2 ? 4 : 0)));
-    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
+    node_conserved_dir<D, J, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
   }
   static_assert(NT >= NC, "the tile's own nodes are the first item of each thread");
 #pragma unroll
@@ -736,11 +781,12 @@ __device__ __forceinline__ void halo_issue(const DevMesh& m, const double* __res
   constexpr int E0 = S::xpitch(J);
   constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
   constexpr int CA = S::T0;                    // extent of the lower cross direction (x)
+  const int tid = phase_tid();
 #pragma unroll
   for (int k = 0; k < H::ITER; ++k) {
     // threads past the last halo node load node NH - 1 again (no branch
     // around the loads) and store nothing
-    const int h0 = threadIdx.x + k * NT;
+    const int h0 = tid + k * NT;
     const int hh = h0 < H::NH ? h0 : H::NH - 1;
     const int layer = hh / H::HL;
     const int r = hh - layer * H::HL;
@@ -751,7 +797,7 @@ __device__ __forceinline__ void halo_issue(const DevMesh& m, const double* __res
     const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
     h.lidx[k] = h0 < H::NH ? t[0] + E0 * ((t[1] + (J == 1 ? 4 : 0)) + E1 * (t[2] + (J == 2 ? 4 : 0)))
                            : -1;
-    node_conserved<D, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, h.u[k]);
+    node_conserved_dir<D, J, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, h.u[k]);
   }
 }
 
@@ -763,7 +809,7 @@ __device__ __forceinline__ void halo_store(const DevMesh& m, const DirHalo<D, TX
   constexpr int E0 = S::xpitch(J);
   constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
   constexpr int NEXT = S::ext(J);
-  const int tid = threadIdx.x;
+  const int tid = phase_tid();
   if (tid < S::NCELL) {
     const int t0 = tid % S::T0, t1 = (tid / S::T0) % S::T1, t2 = tid / (S::T0 * S::T1);
     node_store<D, false>(m, keep, sP, NEXT,
