@@ -115,7 +115,11 @@ amr_status amr_create_hierarchy(const amr_config* cfg, const amr_allocator* allo
 amr_status amr_destroy_hierarchy(amr_hierarchy* h);
 const char* amr_last_error(const amr_hierarchy* h);
 
-/* Sizes and layout queries (no device work). */
+/* Sizes and layout queries (no device work).  amr_patch_offset gives the
+ * state offset of a patch's box; the first level's pool starts after a head
+ * pad of a few doubles (a multiple of nvar) that puts every interior row of
+ * a box, for n_l a multiple of 8, on a 64-byte boundary of a
+ * 256-byte-aligned buffer. */
 amr_status amr_num_patches(const amr_hierarchy* h, int* nactive, int* nleaf);
 amr_status amr_patch_doubles(const amr_hierarchy* h, int level, int64_t* n);
 amr_status amr_state_doubles(const amr_hierarchy* h, int64_t* n);

@@ -303,7 +303,15 @@ void build_devmesh(amr_hierarchy* h) {
   m.theta = c.tag_theta;
   m.cfl = c.cfl;
   m.tag_buffer = c.tag_buffer;
-  long long pool = 0, frp = 0, tg = 0;
+  // Every box row is a multiple of 8 doubles (64 B) when n is, and a
+  // patch's interior starts kNG = 4 doubles into its box rows; a head pad of
+  // 4 mod 8 doubles before the first pool puts every interior row on a 64-byte
+  // boundary (one memory sector for an 8-wide row instead of two).  The pad is
+  // a multiple of nvar, so a box's state offset divided by nvar (its offset
+  // in a per-variable plane, and in the cell-tag layout) stays exact.
+  long long pad = m.nvar;
+  while (pad % 8 != 4) pad += m.nvar;
+  long long pool = pad, frp = 0, tg = pad / m.nvar;
   for (int l = 0; l < c.max_levels; ++l) {
     amr::LevelC& L = m.lv[l];
     L.n = f.n[l];
