@@ -683,21 +683,17 @@ __device__ __forceinline__ void edges_dir(const DevMesh& m, const double* sP, do
   }
 }
 
-// 3D: primitives (conserved values for the characteristic scheme) of the
-// tile extended by 4 nodes on both sides along J, into sP in the
-// extended-box layout.  The tile's own nodes come first in the thread order
-// and the 8 halo layers after them, so that a wave holds nodes of one kind
-// (the tile's own nodes are read straight from the patch); every thread
-// issues the loads of all its nodes before converting any.  For the
-// primitive schemes thread t < NCELL keeps the conserved values of tile
-// node t from direction x in `keep` (they are also the stage input of cell
-// t for the epilogue); their y and z boxes load only the halo layers
-// (halo_issue, halo_store).
-template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE, bool CHAR>
+// 3D, characteristic scheme: the conserved values of the tile extended by 4
+// nodes on both sides along J, into sP in the extended-box layout.  The
+// tile's own nodes come first in the thread order and the 8 halo layers
+// after them, so that a wave holds nodes of one kind (the tile's own nodes
+// are read straight from the patch); every thread issues the loads of all
+// its nodes before storing any.
+template <int D, int TX, int TY, int TZ, int NT, int J, bool FUSE>
 __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restrict__ Uin,
                                          const double* __restrict__ Pin, int n, int full,
                                          const int o[3], const int pc[3], int l,
-                                         const long long* sN, double* sP, double* keep) {
+                                         const long long* sN, double* sP) {
   using S = TileShape<D, TX, TY, TZ>;
   constexpr int NV = D + 2;
   constexpr int E0 = S::xpitch(J);             // row pitch
@@ -709,9 +705,6 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
   constexpr int HL = NC / TJ;                  // nodes of one layer across J
   constexpr int CA = J == 0 ? S::T1 : S::T0;   // extent of the lower cross direction
   constexpr int NNODE = NC + 8 * HL;           // nodes of the extended box
-  // the characteristic scheme's kernel has no registers to spare for it
-  constexpr bool KEEP = !CHAR;
-  static_assert(J == 0 || !KEEP, "y and z boxes of the primitive schemes load their halo only");
   constexpr int ITER = (NNODE + NT - 1) / NT;
   double u[ITER][NV];
   int lidx[ITER];
@@ -739,20 +732,31 @@ __device__ __forceinline__ void load_dir(const DevMesh& m, const double* __restr
                                                 E1 * (t[2] + (J == 2 ? 4 : 0)));
     node_conserved_dir<D, J, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, u[k]);
   }
-  static_assert(NT >= NC, "the tile's own nodes are the first item of each thread");
 #pragma unroll
-  for (int k = 0; k < ITER; ++k) {
-    if (lidx[k] < 0) continue;
-    if (KEEP && k == 0 && (int)threadIdx.x < NC) {
+  for (int k = 0; k < ITER; ++k)
+    if (lidx[k] >= 0) node_store<D, true>(m, u[k], sP, NEXT, lidx[k]);
+}
+
+// 3D primitive schemes: thread t < NCELL loads the conserved values of tile
+// node t once, first in the item (they need no neighbour table), and keeps
+// them in `keep` for the three directions and as the stage input of cell t
+// in the epilogue.
+template <int D, int TX, int TY, int TZ>
+__device__ __forceinline__ void own_load(const double* __restrict__ Pin, int full, const int o[3],
+                                         double* keep) {
+  using S = TileShape<D, TX, TY, TZ>;
+  const int tid = threadIdx.x;
+  if (tid < S::NCELL) {
+    const int t0 = tid % S::T0, t1 = (tid / S::T0) % S::T1, t2 = tid / (S::T0 * S::T1);
+    const int off = box_off<D>(full, o[0] + t0 + NG, o[1] + t1 + NG, o[2] + t2 + NG);
+    const int vs = var_stride<D>(full);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) keep[v] = u[0][v];
-    }
-    node_store<D, CHAR>(m, u[k], sP, NEXT, lidx[k]);
+    for (int v = 0; v < D + 2; ++v) keep[v] = Pin[v * vs + off];
   }
 }
 
-// 3D primitive schemes, directions y and z: the 8 halo layers of the tile
-// extended along J (its own nodes are kept since x).  Their loads are issued
+// 3D primitive schemes: the 8 halo layers of the tile extended along J (its
+// own nodes are kept in registers).  For y and z their loads are issued
 // (halo_issue) before the previous direction's divergence is formed and
 // converted and stored (halo_store) after it, so that they are in flight
 // meanwhile.  Halo node h (layers -4..-1, then T_J..T_J+3, the two other
@@ -777,10 +781,9 @@ __device__ __forceinline__ void halo_issue(const DevMesh& m, const double* __res
                                            DirHalo<D, TX, TY, TZ, NT, J>& h) {
   using S = TileShape<D, TX, TY, TZ>;
   using H = DirHalo<D, TX, TY, TZ, NT, J>;
-  static_assert(J > 0, "direction x loads the whole extended box");
   constexpr int E0 = S::xpitch(J);
   constexpr int E1 = S::T1 + (J == 1 ? 8 : 0);
-  constexpr int CA = S::T0;                    // extent of the lower cross direction (x)
+  constexpr int CA = J == 0 ? S::T1 : S::T0;   // extent of the lower cross direction
   const int tid = phase_tid();
 #pragma unroll
   for (int k = 0; k < H::ITER; ++k) {
@@ -792,10 +795,11 @@ __device__ __forceinline__ void halo_issue(const DevMesh& m, const double* __res
     const int r = hh - layer * H::HL;
     int t[3];
     t[J] = layer < 4 ? layer - 4 : H::TJ + layer - 4;
-    t[0] = r % CA;
+    t[J == 0 ? 1 : 0] = r % CA;
     t[J == 2 ? 1 : 2] = r / CA;
     const int c[3] = {o[0] + t[0], o[1] + t[1], o[2] + t[2]};
-    h.lidx[k] = h0 < H::NH ? t[0] + E0 * ((t[1] + (J == 1 ? 4 : 0)) + E1 * (t[2] + (J == 2 ? 4 : 0)))
+    h.lidx[k] = h0 < H::NH ? (t[0] + (J == 0 ? 4 : 0)) +
+                                 E0 * ((t[1] + (J == 1 ? 4 : 0)) + E1 * (t[2] + (J == 2 ? 4 : 0)))
                            : -1;
     node_conserved_dir<D, J, FUSE>(m, Uin, Pin, n, full, c, pc, l, sN, h.u[k]);
   }
@@ -813,7 +817,8 @@ __device__ __forceinline__ void halo_store(const DevMesh& m, const DirHalo<D, TX
   if (tid < S::NCELL) {
     const int t0 = tid % S::T0, t1 = (tid / S::T0) % S::T1, t2 = tid / (S::T0 * S::T1);
     node_store<D, false>(m, keep, sP, NEXT,
-                         t0 + E0 * ((t1 + (J == 1 ? 4 : 0)) + E1 * (t2 + (J == 2 ? 4 : 0))));
+                         (t0 + (J == 0 ? 4 : 0)) +
+                             E0 * ((t1 + (J == 1 ? 4 : 0)) + E1 * (t2 + (J == 2 ? 4 : 0))));
   }
 #pragma unroll
   for (int k = 0; k < H::ITER; ++k)
@@ -868,8 +873,10 @@ __device__ __forceinline__ void stage_both(const DevMesh& m, double* __restrict_
 // each parent cell is the mean of its 2^D children, summed as the
 // post-stage restriction sums them (x pairs first, then y, then z).  The
 // finest level is never the coarse side of a coarse/fine face, so its values
-// are final once the stage kernel has written them.
-template <int D, int TX, int TY, int TZ, int NT>
+// are final once the stage kernel has written them.  SERIAL: one variable
+// at a time (unrolled, the reads of all variables are issued at once and can
+// take more registers than the primitive schemes' kernels have).
+template <int D, int TX, int TY, int TZ, int NT, bool SERIAL>
 __device__ __forceinline__ void restrict_tile(const DevMesh& m, double* __restrict__ out, int pid,
                                               int l, const int o[3], const double* sR) {
   using S = TileShape<D, TX, TY, TZ>;
@@ -894,14 +901,20 @@ __device__ __forceinline__ void restrict_tile(const DevMesh& m, double* __restri
     auto at = [&](int v, int x, int y, int z) {
       return sR[v * NC + (2 * a + x) + S::T0 * ((2 * b + y) + S::T1 * (2 * c + z))];
     };
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    auto one = [&](int v) {
       auto xsum = [&](int y, int z) { return at(v, 0, y, z) + at(v, 1, y, z); };
       double r;
       if constexpr (D == 1) r = xsum(0, 0) * 0.5;
       else if constexpr (D == 2) r = (xsum(0, 0) + xsum(1, 0)) * 0.25;
       else r = ((xsum(0, 0) + xsum(1, 0)) + (xsum(0, 1) + xsum(1, 1))) * 0.125;
       Pp[v * vsc + dst] = r;
+    };
+    if constexpr (SERIAL) {
+#pragma unroll 1
+      for (int v = 0; v < NV; ++v) one(v);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) one(v);
     }
   }
 }
@@ -944,6 +957,8 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
   // from the first node load (see load_dir)
   constexpr bool KEPT = !UNION && !CHAR;
   double keep[NV], un0[NV];
+  // the tile's own nodes first: their loads need no neighbour table
+  if constexpr (KEPT) own_load<D, TX, TY, TZ>(Pin, full, o, keep);
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
     __syncthreads();
@@ -963,8 +978,13 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     // 3D, direction by direction: the next direction's nodes are loaded in
     // the phase that forms the previous direction's divergence (sP is free
     // once the edges are done, sF is read), two block barriers per direction
-    load_dir<D, TX, TY, TZ, NT, 0, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
-                                                   keep);
+    if constexpr (KEPT) {
+      DirHalo<D, TX, TY, TZ, NT, 0> h;
+      halo_issue<D, TX, TY, TZ, NT, 0, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, h);
+      halo_store<D, TX, TY, TZ, NT, 0>(m, h, keep, sP);
+    } else {
+      load_dir<D, TX, TY, TZ, NT, 0, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
+    }
     __syncthreads();
     edges_dir<D, TX, TY, TZ, NT, 0, false, CHAR>(m, sP, sF);
     __syncthreads();
@@ -974,8 +994,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
       cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
       halo_store<D, TX, TY, TZ, NT, 1>(m, h, keep, sP);
     } else {
-      load_dir<D, TX, TY, TZ, NT, 1, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
-                                                     keep);
+      load_dir<D, TX, TY, TZ, NT, 1, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
       cells_at<D, TX, TY, TZ, NT, 0>(sF, frp, n, o, acc, L.inv_h, wmask);
     }
     __syncthreads();
@@ -987,8 +1006,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
       cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
       halo_store<D, TX, TY, TZ, NT, 2>(m, h, keep, sP);
     } else {
-      load_dir<D, TX, TY, TZ, NT, 2, FUSE, CHAR>(m, Uin, Pin, n, full, o, pc, l, sN, sP,
-                                                     keep);
+      load_dir<D, TX, TY, TZ, NT, 2, FUSE>(m, Uin, Pin, n, full, o, pc, l, sN, sP);
       cells_at<D, TX, TY, TZ, NT, 1>(sF, frp, n, o, acc, L.inv_h, wmask);
     }
     __syncthreads();
@@ -1084,7 +1102,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
   }
   if (restrict_here) {
     __syncthreads();
-    restrict_tile<D, TX, TY, TZ, NT>(m, out, pid, l, o, sR);
+    restrict_tile<D, TX, TY, TZ, NT, KEPT>(m, out, pid, l, o, sR);
   }
 }
 
