@@ -953,11 +953,11 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
     for (int v = 0; v < NV; ++v) acc[cc][v] = 0.0;
 
   const int pc[3] = {m.coord[3 * pid], m.coord[3 * pid + 1], m.coord[3 * pid + 2]};
-  // 3D primitive schemes: the stage input of this thread's own cell, kept
-  // from the first node load (see load_dir)
+  // 3D primitive schemes: the conserved values of this thread's tile node,
+  // loaded first (their loads need no neighbour table) and kept for the three
+  // directions and the epilogue (own_load), and U^n of its cell
   constexpr bool KEPT = !UNION && !CHAR;
   double keep[NV], un0[NV];
-  // the tile's own nodes first: their loads need no neighbour table
   if constexpr (KEPT) own_load<D, TX, TY, TZ>(Pin, full, o, keep);
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
