@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
                                                    o[2] + t2 + NG);
           const int vs = var_stride<D>(full);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) un0[v] = p[v * vs];
+          for (int v = 0; v < NV; ++v) un0[v] = __builtin_nontemporal_load(p + v * vs);
         }
       }
     }
@@ -1086,7 +1086,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
         const double ui = (KEPT && cc == 0) ? keep[v] : Uin[a];
         r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
-      out[a] = r[v];
+      __builtin_nontemporal_store(r[v], out + a);
       if (restrict_here) sR[v * S::NCELL + cell] = r[v];
     }
     if (want_rate) {
