@@ -1086,7 +1086,12 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
         const double ui = (KEPT && cc == 0) ? keep[v] : Uin[a];
         r[v] = fma(mode == kModeStage2 ? 0.25 : c23, fma(dt, Lv, ui) - un, un);
       }
-      __builtin_nontemporal_store(r[v], out + a);
+      // 3D: a non-temporal store, which keeps the stage input's halo rows
+      // in L2 for the neighbouring tiles
+      if constexpr (UNION)
+        out[a] = r[v];
+      else
+        __builtin_nontemporal_store(r[v], out + a);
       if (restrict_here) sR[v * S::NCELL + cell] = r[v];
     }
     if (want_rate) {
