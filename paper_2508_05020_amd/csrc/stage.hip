@@ -958,6 +958,7 @@ __device__ __forceinline__ void stage_item(const DevMesh& m, int mode,
   // directions and the epilogue (own_load), and U^n of its cell
   constexpr bool KEPT = !UNION && !CHAR;
   double keep[NV], un0[NV];
+  static_assert(!KEPT || NT >= S::NCELL, "a thread per tile node holds its values");
   if constexpr (KEPT) own_load<D, TX, TY, TZ>(Pin, full, o, keep);
   if constexpr (FUSE) {
     load_neighbours<D>(m, l, pc, sN);
